@@ -1,0 +1,174 @@
+/*
+ * og.h -- ordered (bucketed) shortest-path processing on MI355X (gfx950).
+ *
+ * A C ABI over hand-written HIP kernels for Delta-stepping with eager
+ * bucket updates and bucket fusion, as described in "Optimizing Ordered
+ * Graph Algorithms with GraphIt" (CGO 2020):
+ *   - section 2: priority coarsening, bucket index = floor(priority / Delta);
+ *   - section 3.2: eager bucket update (each worker inserts improved
+ *     vertices into its own buckets; the smallest non-empty bucket across
+ *     workers is processed next);
+ *   - section 3.3: bucket fusion (a worker keeps processing its local copy
+ *     of the current bucket, without a global synchronisation, while it is
+ *     non-empty and smaller than a threshold);
+ *   - section 6.1: SSSP, wBFS (Delta fixed to 1), PPSP (stop on entering
+ *     bucket i with i*Delta >= best distance to the target found so far)
+ *     and A* (priority = distance so far + per-vertex estimate).
+ * The schedule fields mirror the scheduling-language table of section 4.2
+ * (configApplyPriorityUpdate, ...Delta, configBucketFusionThreshold,
+ * configNumBuckets).
+ *
+ * Conventions
+ *   - Every array argument is DEVICE memory owned by the caller, except
+ *     og_stats and the og_graph / og_schedule structs themselves, which are
+ *     host memory.  The library allocates nothing: scratch space is the
+ *     caller's workspace buffer, sized by og_workspace_bytes().
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it.  Unless OG_FLAG_ASYNC is set the call waits
+ *     for the stream before returning and reports the device-side status.
+ *   - Graphs are directed CSR: the out-edges of v are col[row_ptr[v] ..
+ *     row_ptr[v+1]) with weights w[...].  An undirected graph stores both
+ *     directions.  Weights are int32 >= 0; a negative weight is reported as
+ *     OG_ERR_NEGATIVE_WEIGHT when OG_FLAG_VALIDATE is set and otherwise makes
+ *     the result undefined (it surfaces as OG_ERR_OVERFLOW).
+ *   - Distances are int32 with INF = INT32_MAX for unreachable vertices.  A
+ *     finite path length that does not fit below INT32_MAX is reported as
+ *     OG_ERR_OVERFLOW (the outputs are then undefined).
+ *   - Predecessors (optional, may be NULL) follow a canonical rule, so they
+ *     are unique: pred[v] = the smallest u with an edge (u,v) and
+ *     dist[u] + w(u,v) == dist[v]; pred[src] = src; -1 if v is unreachable.
+ *   - Calls on one workspace must not overlap; distinct workspaces may run
+ *     concurrently on distinct streams.
+ */
+#ifndef OG_H
+#define OG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t og_status;
+#define OG_OK 0
+#define OG_ERR_INVALID_ARG (-1)     /* bad argument; nothing was launched       */
+#define OG_ERR_NEGATIVE_WEIGHT (-2) /* OG_FLAG_VALIDATE found a weight < 0      */
+#define OG_ERR_OVERFLOW (-3)        /* a path length reached INT32_MAX          */
+#define OG_ERR_WORKSPACE (-4)       /* ws_bytes too small, or a queue filled up;
+                                       og_stats.queue_needed tells how many
+                                       entries per queue would have been used  */
+#define OG_ERR_HIP (-5)             /* a HIP runtime call failed                */
+#define OG_ERR_ROUND_LIMIT (-6)     /* schedule.max_rounds reached              */
+
+/* Schedule flags. */
+#define OG_FLAG_VALIDATE 1u /* scan weights for negatives before running      */
+#define OG_FLAG_ASYNC 2u    /* do not wait; read the status later with
+                               og_read_stats() after synchronising the stream */
+
+/* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
+#define OG_EAGER_NO_FUSION 0
+#define OG_EAGER_WITH_FUSION 1
+
+/* Engines. */
+#define OG_ENGINE_PERSISTENT 0 /* one cooperative launch, device-wide barrier
+                                  between rounds (default)                   */
+#define OG_ENGINE_HOST_ROUNDS 1 /* one kernel launch per round               */
+
+/* Borrowed view of a directed CSR graph (device arrays). */
+typedef struct og_graph {
+  int32_t n;               /* vertices, >= 1                                  */
+  int64_t m;               /* directed edges, row_ptr[n]                      */
+  const int64_t* row_ptr;  /* [n+1], row_ptr[0] = 0, non-decreasing           */
+  const int32_t* col;      /* [m], destinations in [0, n)                     */
+  const int32_t* w;        /* [m], weights >= 0                               */
+} og_graph;
+
+/* How to run (section 4.2).  Zero fields take the defaults documented here;
+ * og_default_schedule() fills them in explicitly. */
+typedef struct og_schedule {
+  int32_t delta;            /* Delta >= 1: bucket = floor(priority/Delta)     */
+  int32_t update;           /* OG_EAGER_WITH_FUSION (default) or ..._NO_FUSION */
+  int32_t fusion_threshold; /* a workgroup keeps processing its local current
+                               bucket while it holds fewer entries than this
+                               (0 = 1024; capped at the LDS queue, 2048)      */
+  int32_t window_buckets;   /* buckets materialised at once, 2..64 (0 = 16);
+                               later ones wait in an overflow ("far") queue   */
+  int32_t engine;           /* OG_ENGINE_PERSISTENT (default) / _HOST_ROUNDS  */
+  int32_t max_rounds;       /* stop with OG_ERR_ROUND_LIMIT after this many
+                               rounds (0 = unlimited)                         */
+  int32_t workgroups;       /* workgroups to launch (0 = all co-resident)     */
+  uint32_t flags;           /* OG_FLAG_*                                      */
+  int64_t queue_capacity;   /* entries per global queue (0 = n + m/8)         */
+} og_schedule;
+
+/* Per-call counters (host struct). */
+typedef struct og_stats {
+  og_status status;
+  int32_t workgroups;       /* workgroups launched                            */
+  int64_t rounds;           /* global synchronisations (barriers or launches) */
+  int64_t buckets;          /* distinct buckets processed                     */
+  int64_t relaxations;      /* edges examined                                 */
+  int64_t improvements;     /* successful atomic minimum updates              */
+  int64_t pushes_local;     /* entries appended to an LDS (fused) queue       */
+  int64_t pushes_global;    /* entries appended to a global queue             */
+  int64_t far_pushes;       /* of which went to the overflow queue            */
+  int64_t reached_vertices; /* dist < INF (computed when pred or stats given) */
+  int64_t reached_edges;    /* sum of out-degrees of reached vertices         */
+  int64_t queue_needed;     /* largest queue fill requested, in entries       */
+} og_stats;
+
+/* Library version, (major << 16) | minor. */
+int32_t og_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* og_status_string(og_status s);
+
+/* Fills *s with the defaults (delta = 1 unless set by the caller before the
+ * call is irrelevant: every field is overwritten). */
+og_status og_default_schedule(og_schedule* s);
+
+/* Workspace bytes og_sssp & co. need for this graph and schedule (0 if the
+ * arguments are invalid).  Aligned to 256 bytes. */
+size_t og_workspace_bytes(const og_graph* g, const og_schedule* s);
+
+/* Single-source shortest paths by Delta-stepping (sections 3.2, 3.3).
+ *   src      : source vertex in [0, n)
+ *   dist     : [n] output distances
+ *   pred     : [n] output canonical predecessors, or NULL
+ *   ws       : device workspace of ws_bytes >= og_workspace_bytes(g, s)
+ *   stats    : host counters, or NULL
+ * Returns OG_OK or an error code (see above). */
+og_status og_sssp(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
+                  void* ws, size_t ws_bytes, og_stats* stats, void* stream);
+
+/* Weighted BFS (section 6.1): og_sssp with Delta forced to 1; intended for
+ * positive integer weights in [1, log n). */
+og_status og_wbfs(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
+                  void* ws, size_t ws_bytes, og_stats* stats, void* stream);
+
+/* Point-to-point shortest path (section 6.1): stops before processing a
+ * bucket i with i*Delta >= dist[dst].  Only dist[dst] and the predecessor
+ * chain from dst back to src are defined on return (other entries hold
+ * upper bounds).  dist[dst] = INT32_MAX if dst is unreachable. */
+og_status og_ppsp(const og_graph* g, int32_t src, int32_t dst, const og_schedule* s, int32_t* dist,
+                  int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream);
+
+/* A* (section 6.1): as og_ppsp, but a vertex v reached at distance d is
+ * bucketed by floor((d + h[v]) / Delta).  h ([n], device, int32 >= 0) must
+ * be admissible (never above the true remaining distance to dst, so
+ * h[dst] = 0) for dist[dst] to be exact. */
+og_status og_astar(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, const og_schedule* s,
+                   int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats,
+                   void* stream);
+
+/* Reads the status and counters of the last call made with workspace ws
+ * (device) into *stats (host); used after an OG_FLAG_ASYNC call once the
+ * stream has been synchronised.  Blocking copy on stream. */
+og_status og_read_stats(const void* ws, og_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OG_H */

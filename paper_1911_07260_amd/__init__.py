@@ -1,0 +1,177 @@
+"""Ordered (bucketed) shortest-path processing on MI355X.
+
+Python face of libog.so (include/og.h).  PyTorch supplies device memory and
+streams only; every step of the computation runs in the library's HIP
+kernels.  Functions mirror the C ABI:
+
+    sssp(graph, src, schedule)        og_sssp
+    wbfs(graph, src, schedule)        og_wbfs   (Delta forced to 1)
+    ppsp(graph, src, dst, schedule)   og_ppsp
+    astar(graph, src, dst, h, sched)  og_astar
+
+Each returns ``(dist, pred, stats)`` with int32 device tensors (pred is None
+when not requested) and a dict of counters.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field, fields
+
+import torch
+
+from . import _lib
+from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_HOST_ROUNDS, OG_ENGINE_PERSISTENT,
+                   OG_ERR_INVALID_ARG, OG_ERR_WORKSPACE, OG_FLAG_ASYNC, OG_FLAG_VALIDATE, OG_OK, OgError,
+                   OgGraph, OgSchedule, OgStats)
+
+INF = 2**31 - 1
+
+__all__ = [
+    "DeviceGraph", "Schedule", "Workspace", "sssp", "wbfs", "ppsp", "astar", "workspace_bytes",
+    "status_string", "version", "INF", "OgError",
+]
+
+
+@dataclass
+class Schedule:
+    """og_schedule (section 4.2 scheduling options).  Zero = library default."""
+    delta: int = 1
+    update: int = OG_EAGER_WITH_FUSION
+    fusion_threshold: int = 0
+    window_buckets: int = 0
+    engine: int = OG_ENGINE_PERSISTENT
+    max_rounds: int = 0
+    workgroups: int = 0
+    flags: int = 0
+    queue_capacity: int = 0
+
+    @property
+    def fused(self) -> bool:
+        return self.update == OG_EAGER_WITH_FUSION
+
+    def to_c(self) -> OgSchedule:
+        return OgSchedule(**{f.name: int(getattr(self, f.name)) for f in fields(self)})
+
+
+class DeviceGraph:
+    """Directed CSR graph resident on a device (int64 row_ptr, int32 col, w)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, w: torch.Tensor):
+        assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32 and w.dtype == torch.int32
+        assert row_ptr.is_contiguous() and col.is_contiguous() and w.is_contiguous()
+        self.row_ptr, self.col, self.w = row_ptr, col, w
+        self.n = row_ptr.numel() - 1
+        self.m = col.numel()
+
+    @classmethod
+    def from_host(cls, g, device="cuda"):
+        """From any object with numpy row_ptr / col / w (e.g. graphgen.Graph)."""
+        rp = torch.from_numpy(g.row_ptr).to(device=device, dtype=torch.int64).contiguous()
+        col = torch.from_numpy(g.col).to(device=device, dtype=torch.int32).contiguous()
+        w = torch.from_numpy(g.w).to(device=device, dtype=torch.int32).contiguous()
+        return cls(rp, col, w)
+
+    @property
+    def device(self):
+        return self.row_ptr.device
+
+    def to_c(self) -> OgGraph:
+        return OgGraph(self.n, self.m, self.row_ptr.data_ptr(),
+                       self.col.data_ptr() if self.m else None,
+                       self.w.data_ptr() if self.m else None)
+
+
+def version() -> int:
+    return int(_lib.load().og_version())
+
+
+def status_string(status: int) -> str:
+    return _lib.load().og_status_string(int(status)).decode()
+
+
+def workspace_bytes(graph: DeviceGraph, schedule: Schedule) -> int:
+    lib = _lib.load()
+    g = graph.to_c()
+    s = schedule.to_c()
+    return int(lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s)))
+
+
+class Workspace:
+    """A device byte buffer reused across calls (grown on demand)."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf: torch.Tensor | None = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def _workspace(graph: DeviceGraph, schedule: Schedule, ws: Workspace | None):
+    nbytes = workspace_bytes(graph, schedule)
+    if nbytes == 0:
+        raise OgError(OG_ERR_INVALID_ARG, "og_workspace_bytes", _lib.load())
+    if ws is None:
+        key = str(graph.device)
+        ws = _default_ws.setdefault(key, Workspace(graph.device))
+    return ws.get(nbytes), nbytes
+
+
+def _call(fn_name, graph, args_mid, schedule, want_pred, ws, stream, out_dist=None, out_pred=None,
+          check=True):
+    lib = _lib.load()
+    schedule = schedule or Schedule()
+    n = graph.n
+    dev = graph.device
+    dist = out_dist if out_dist is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    pred = out_pred if out_pred is not None else (
+        torch.empty(n, dtype=torch.int32, device=dev) if want_pred else None)
+    buf, nbytes = _workspace(graph, schedule, ws)
+    g = graph.to_c()
+    s = schedule.to_c()
+    st = OgStats()
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    handle = ctypes.c_void_p(stream.cuda_stream)
+    fn = getattr(lib, fn_name)
+    status = fn(ctypes.byref(g), *args_mid, ctypes.byref(s), ctypes.c_void_p(dist.data_ptr()),
+                ctypes.c_void_p(pred.data_ptr()) if pred is not None else None,
+                ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(buf.numel()), ctypes.byref(st), handle)
+    stats = st.as_dict()
+    stats["status"] = int(status)
+    if check and status != OG_OK:
+        raise OgError(status, fn_name, lib)
+    return dist, pred, stats
+
+
+def sssp(graph: DeviceGraph, src: int, schedule: Schedule | None = None, pred: bool = True,
+         ws: Workspace | None = None, stream=None, **kw):
+    """Single-source shortest paths (og_sssp)."""
+    return _call("og_sssp", graph, [int(src)], schedule, pred, ws, stream, **kw)
+
+
+def wbfs(graph: DeviceGraph, src: int, schedule: Schedule | None = None, pred: bool = True,
+         ws: Workspace | None = None, stream=None, **kw):
+    """Weighted BFS (og_wbfs): Delta = 1."""
+    return _call("og_wbfs", graph, [int(src)], schedule, pred, ws, stream, **kw)
+
+
+def ppsp(graph: DeviceGraph, src: int, dst: int, schedule: Schedule | None = None, pred: bool = True,
+         ws: Workspace | None = None, stream=None, **kw):
+    """Point-to-point shortest path (og_ppsp): only dist[dst] and dst's
+    predecessor chain are defined."""
+    return _call("og_ppsp", graph, [int(src), int(dst)], schedule, pred, ws, stream, **kw)
+
+
+def astar(graph: DeviceGraph, src: int, dst: int, h: torch.Tensor, schedule: Schedule | None = None,
+          pred: bool = True, ws: Workspace | None = None, stream=None, **kw):
+    """A* (og_astar) with per-vertex estimate h (int32 device tensor)."""
+    assert h.dtype == torch.int32 and h.is_contiguous() and h.numel() == graph.n
+    return _call("og_astar", graph, [int(src), int(dst), ctypes.c_void_p(h.data_ptr())], schedule, pred,
+                 ws, stream, **kw)

@@ -1,0 +1,1001 @@
+// Delta-stepping with eager bucket updates and bucket fusion on gfx950.
+//
+// Paper mapping ("Optimizing Ordered Graph Algorithms with GraphIt"):
+//   - A "thread" of the eager algorithm (section 3.2) is a workgroup here.
+//     Its thread-local buckets are an LDS ring holding the local copy of the
+//     current bucket; later buckets go to device-wide bucket queues (a
+//     window of K materialised buckets plus an overflow "far" queue, the
+//     same idea as keeping only a few buckets materialised in section 5.1).
+//   - A round processes the round's input list (the current bucket) with
+//     dynamic chunking across workgroups; every relaxation is a 32-bit
+//     atomic minimum on dist (section 3.2, Dist[e.dst] = min(...)), and an
+//     improved vertex is inserted at once into the bucket of its new
+//     priority floor(d / Delta) (eager update, section 2 coarsening).
+//   - Bucket fusion (section 3.3): after its share of the round input, a
+//     workgroup keeps draining its LDS current-bucket ring with no global
+//     synchronisation while the ring holds fewer entries than the fusion
+//     threshold; a larger local bucket is published to the global list for
+//     the next round, which redistributes it over all workgroups.
+//   - The global minimum-bucket selection (section 3.2, getGlobalMinBucket;
+//     section 5.2, cross-thread minimum) is done once per round by the last
+//     workgroup to arrive at the device-wide barrier.
+//   - Stale entries are never removed from queues: entries carry (v, d) and
+//     are skipped when d > dist[v] (insert without delete).
+//
+// Correctness does not depend on the cache coherence of plain loads of
+// dist: dist only decreases during a call, a plain load returns some past
+// value (>= the current one), and every decision that matters is taken on
+// the return value of the device-scope atomic minimum or on the distance
+// carried in the queue entry.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "og.h"
+
+namespace og {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kWaves = kBlock / kWave;
+constexpr int kLq = 2048;  // LDS ring entries (power of two)
+constexpr int kKmax = 64;
+constexpr int kDefaultK = 16;
+constexpr int kDefaultThreshold = 1024;
+constexpr size_t kCtlBytes = 4096;
+constexpr unsigned kNoBucket = 0xffffffffu;
+constexpr int kInf = INT_MAX;
+
+enum : int { kInWin = 0, kInSpill = 1, kInFar = 2 };
+
+// Device-side control block at the start of the workspace.
+struct Ctl {
+  unsigned bar_arrive;  // barrier arrivals in the current round
+  unsigned bar_gen;     // barrier generation
+  unsigned cur;         // current bucket
+  int in_kind;          // round input: window slot / spill list / far list
+  int in_index;
+  unsigned in_count;
+  unsigned in_head;  // dynamic chunk cursor into the round input
+  unsigned chunk;
+  int done;
+  int status;
+  int spill_out;  // spill list receiving current-bucket pushes this round
+  int far_in;     // far list holding pending overflow entries
+  unsigned win_hi;  // buckets >= win_hi go to the far list
+  unsigned round;
+  unsigned buckets;
+  unsigned pad0;
+  unsigned win_tail[kKmax];
+  unsigned spill_tail[2];
+  unsigned far_tail[2];
+  unsigned far_min[2];
+  unsigned long long need;
+  unsigned long long st_relax, st_improve, st_push_local, st_push_global, st_far;
+  unsigned long long st_reached_v, st_reached_e;
+};
+static_assert(sizeof(Ctl) <= kCtlBytes, "control block too large");
+
+struct Args {
+  const long long* row_ptr;
+  const int* col;
+  const int* w;
+  int* dist;
+  const int* h;  // A* estimate or nullptr
+  int n;
+  int target;  // -1 for SSSP / wBFS
+  unsigned delta;
+  int shift;  // log2(delta) when delta is a power of two, else -1
+  int K;      // window buckets (power of two)
+  unsigned cap;
+  int fused;
+  unsigned threshold;
+  unsigned max_rounds;
+  int nwg;
+  Ctl* ctl;
+  int2* win;
+  int2* spill;
+  int2* far;
+};
+
+struct Counters {
+  unsigned long long relax = 0, improve = 0, push_local = 0, push_global = 0, far = 0;
+};
+
+struct Smem {
+  int2 lq[kLq];
+  long long bstart[kBlock];
+  int boff[kBlock];
+  int bd[kBlock];
+  int wsum[kWaves];
+  unsigned lq_head, lq_tail;
+  int mode, nb;
+  unsigned gbase;
+  int exhausted;
+  int last;
+  int tbound;
+  unsigned gen;
+  // snapshot of the control block for this round
+  unsigned cur, in_count, chunk, win_hi;
+  int in_kind, in_index, done, spill_out, far_out;
+};
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+__device__ __forceinline__ unsigned bucket_of(const Args& a, int v, unsigned d) {
+  unsigned key = d;
+  if (a.h) key += (unsigned)a.h[v];  // both < 2^31: no wrap
+  return a.shift >= 0 ? (key >> a.shift) : (key / a.delta);
+}
+
+__device__ __forceinline__ unsigned sat_add(unsigned x, unsigned y) {
+  return x > 0xffffffffu - y ? 0xffffffffu : x + y;
+}
+
+__device__ __forceinline__ void set_status(Ctl* c, int st) { atomicCAS(&c->status, 0, st); }
+
+__device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
+  int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
+  return base + (size_t)index * a.cap;
+}
+
+// Block-wide exclusive prefix sum of x; *total receives the sum.
+__device__ int block_excl_scan(int x, Smem& s, int* total) {
+  const int lane = (int)lane_id(), wid = threadIdx.x / kWave;
+  int v = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) s.wsum[wid] = v;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    int t = s.wsum[i];
+    pre += i < wid ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + v - x;
+}
+
+// Wave-cooperative append of (v, d) entries to global queues.  Targets:
+// 0..K-1 window slots, K = this round's spill list, K+1 = far list.  All 64
+// lanes must call it together.  A full window slot or spill list falls back
+// to the far list; a full far list sets OG_ERR_WORKSPACE and drops the entry.
+__device__ void wave_push_global(const Args& a, const Smem& s, Counters& c, bool has, int tgt, int v,
+                                 int d, unsigned b) {
+  Ctl* ctl = a.ctl;
+  const int K = a.K;
+  for (;;) {
+    const unsigned long long m = __ballot(has);
+    if (m == 0) break;
+    const int leader = __ffsll((long long)m) - 1;
+    const int t = __shfl(tgt, leader);
+    const bool mine = has && tgt == t;
+    const unsigned long long mm = __ballot(mine);
+    unsigned* tail;
+    int2* q;
+    if (t < K) {
+      tail = &ctl->win_tail[t];
+      q = a.win + (size_t)t * a.cap;
+    } else if (t == K) {
+      tail = &ctl->spill_tail[s.spill_out];
+      q = a.spill + (size_t)s.spill_out * a.cap;
+    } else {
+      tail = &ctl->far_tail[s.far_out];
+      q = a.far + (size_t)s.far_out * a.cap;
+    }
+    unsigned base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(tail, (unsigned)__popcll(mm));
+    base = __shfl(base, leader);
+    if (mine) {
+      const unsigned pos = base + (unsigned)__popcll(mm & lanemask_lt());
+      if (pos < a.cap && pos >= base) {
+        q[pos] = make_int2(v, d);
+        c.push_global++;
+        if (t == K + 1) {
+          c.far++;
+          atomicMin(&ctl->far_min[s.far_out], b);
+        }
+        has = false;
+      } else if (t == K + 1) {
+        set_status(ctl, OG_ERR_WORKSPACE);
+        has = false;
+      } else {
+        tgt = K + 1;
+      }
+    }
+  }
+}
+
+// Routes one improved vertex per lane: the current bucket goes to the LDS
+// ring when fusing (falling back to the spill list when the ring is full),
+// later buckets to their window slot or the far list.
+__device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v, int d, unsigned b) {
+  const unsigned cur = s.cur;
+  if (has && b < cur) b = cur;  // only an inconsistent A* estimate gets here
+  const bool local = has && a.fused && b == cur;
+  const unsigned long long m = __ballot(local);
+  if (m) {
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(&s.lq_tail, (unsigned)__popcll(m));
+    base = __shfl(base, leader);
+    if (local) {
+      const unsigned pos = base + (unsigned)__popcll(m & lanemask_lt());
+      if (pos - s.lq_head < (unsigned)kLq) {
+        s.lq[pos & (kLq - 1)] = make_int2(v, d);
+        c.push_local++;
+        has = false;
+      }
+    }
+  }
+  int tgt = 0;
+  if (has) tgt = b == cur ? a.K : (b < s.win_hi ? (int)(b & (unsigned)(a.K - 1)) : a.K + 1);
+  wave_push_global(a, s, c, has, tgt, v, d, b);
+}
+
+// Relaxes the out-edges of one batch of up to kBlock entries (v, d); lane i
+// holds entry i (v < 0: none).  Edges of the batch are spread evenly over the
+// workgroup (flat expansion with a binary search over degree offsets), so a
+// high-degree vertex is shared by all lanes.
+__device__ void process_batch(const Args& a, Smem& s, Counters& c, int v, int d, bool from_global) {
+  const int tid = threadIdx.x;
+  int deg = 0;
+  long long start = 0;
+  bool repush = false;
+  unsigned rb = 0;
+  if (v >= 0) {
+    const int cv = a.dist[v];
+    bool live = d <= cv;
+    if (live && from_global) {
+      rb = bucket_of(a, v, (unsigned)d);
+      if (rb > s.cur) {
+        repush = true;  // a far-list entry that belongs to a later bucket
+        live = false;
+      }
+    }
+    if (live && a.target >= 0) {
+      const unsigned key = a.h ? (unsigned)d + (unsigned)a.h[v] : (unsigned)d;
+      if (key >= (unsigned)s.tbound) live = false;  // cannot improve the target
+    }
+    if (live) {
+      start = a.row_ptr[v];
+      deg = (int)(a.row_ptr[v + 1] - start);
+    }
+  }
+  {
+    int tgt = 0;
+    if (repush) tgt = rb < s.win_hi ? (int)(rb & (unsigned)(a.K - 1)) : a.K + 1;
+    wave_push_global(a, s, c, repush, tgt, v, d, rb);
+  }
+  int total;
+  const int off = block_excl_scan(deg, s, &total);
+  s.boff[tid] = off;
+  s.bstart[tid] = start;
+  s.bd[tid] = d;
+  __syncthreads();
+  const int nb = s.nb;
+  const int tb = s.tbound;
+  for (int base = 0; base < total; base += kBlock) {
+    const int e = base + tid;
+    bool has = false;
+    int u = 0;
+    unsigned nd = 0, b = 0;
+    if (e < total) {
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.boff[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      const long long edge = s.bstart[lo] + (long long)(e - s.boff[lo]);
+      u = a.col[edge];
+      const int wt = a.w[edge];
+      c.relax++;
+      nd = (unsigned)s.bd[lo] + (unsigned)wt;
+      if (wt < 0) {
+        set_status(a.ctl, OG_ERR_NEGATIVE_WEIGHT);
+      } else if (nd >= (unsigned)kInf) {
+        set_status(a.ctl, OG_ERR_OVERFLOW);
+      } else {
+        bool go = (int)nd < a.dist[u];
+        unsigned key = nd;
+        if (go && a.target >= 0) {
+          if (a.h) key = nd + (unsigned)a.h[u];
+          go = key < (unsigned)tb;
+        }
+        if (go) {
+          const int old = atomicMin(&a.dist[u], (int)nd);
+          if ((int)nd < old) {
+            c.improve++;
+            has = true;
+            b = a.shift >= 0 ? ((a.h ? key : nd) >> a.shift) : ((a.h ? key : nd) / a.delta);
+          }
+        }
+      }
+    }
+    route_push(a, s, c, has, u, (int)nd, b);
+  }
+}
+
+// Publishes the LDS ring (the local current bucket) to the global spill
+// list so the next round spreads it over all workgroups (section 3.3: a
+// local bucket at or above the threshold is copied to the global bucket).
+__device__ void publish_local(const Args& a, Smem& s, Counters& c) {
+  const int tid = threadIdx.x;
+  const unsigned h = s.lq_head, cnt = s.lq_tail - s.lq_head;
+  if (tid == 0) s.gbase = atomicAdd(&a.ctl->spill_tail[s.spill_out], cnt);
+  __syncthreads();
+  const unsigned gb = s.gbase;
+  int2* q = a.spill + (size_t)s.spill_out * a.cap;
+  for (unsigned i0 = 0; i0 < cnt; i0 += kBlock) {
+    const unsigned i = i0 + tid;
+    bool spill_far = false;
+    int2 e = make_int2(0, 0);
+    if (i < cnt) {
+      e = s.lq[(h + i) & (kLq - 1)];
+      const unsigned pos = gb + i;
+      if (pos < a.cap && pos >= gb) {
+        q[pos] = e;
+        c.push_global++;
+      } else {
+        spill_far = true;
+      }
+    }
+    wave_push_global(a, s, c, spill_far, a.K + 1, e.x, e.y, s.cur);
+  }
+  __syncthreads();
+  if (tid == 0) s.lq_head = s.lq_tail = 0;
+}
+
+// One round: the round input list, then (fused) the local current bucket.
+__device__ void run_round(const Args& a, Smem& s, Counters& c) {
+  const int tid = threadIdx.x;
+  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  if (tid == 0) {
+    s.lq_head = s.lq_tail = 0;
+    s.exhausted = 0;
+  }
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) {
+      if (s.lq_tail - s.lq_head > (unsigned)kLq) s.lq_tail = s.lq_head + kLq;  // burned reservations
+      const unsigned lsize = s.lq_tail - s.lq_head;
+      s.mode = 0;
+      if (lsize > 0 && lsize >= a.threshold) {
+        s.mode = 3;
+      } else if (lsize > 0) {
+        s.mode = 1;
+        s.nb = (int)(lsize < (unsigned)kBlock ? lsize : (unsigned)kBlock);
+      } else if (!s.exhausted) {
+        const unsigned base = atomicAdd(&a.ctl->in_head, s.chunk);
+        if (base < s.in_count) {
+          s.mode = 2;
+          const unsigned left = s.in_count - base;
+          s.nb = (int)(left < s.chunk ? left : s.chunk);
+          s.gbase = base;
+        } else {
+          s.exhausted = 1;
+        }
+      }
+      if (a.target >= 0 && s.mode != 0) s.tbound = a.dist[a.target];
+    }
+    __syncthreads();
+    const int mode = s.mode;
+    if (mode == 0) break;
+    if (mode == 3) {
+      publish_local(a, s, c);
+      continue;
+    }
+    const int nb = s.nb;
+    int v = -1, d = 0;
+    if (tid < nb) {
+      const int2 e = mode == 1 ? s.lq[(s.lq_head + tid) & (kLq - 1)] : in[s.gbase + tid];
+      v = e.x;
+      d = e.y;
+    }
+    __syncthreads();
+    if (tid == 0 && mode == 1) s.lq_head += nb;
+    __syncthreads();
+    process_batch(a, s, c, v, d, mode == 2);
+  }
+}
+
+// Bucket decision, executed by wave 0 of the last workgroup to finish a
+// round, while every other workgroup waits (persistent engine) or has
+// exited (host-driven engine).  Chooses the next round's input:
+//   1. far entries of the current bucket (overflow),
+//   2. the window slot of the current bucket (after such a far round),
+//   3. the spill list: the same bucket needs another round,
+//   4. otherwise the next non-empty bucket (section 3.2: smallest bucket
+//      across workers), or stop (nothing left, or PPSP / A*: that bucket's
+//      lower bound i*Delta already reaches the target's distance).
+__device__ void decide(const Args& a) {
+  Ctl* c = a.ctl;
+  const int lane = (int)lane_id();
+  const int K = a.K;
+  auto ld = [](const unsigned* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+  const unsigned cur = c->cur;
+  const int in_kind = c->in_kind, in_index = c->in_index;
+  const unsigned round = c->round + 1;
+  int status = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int far_in = in_kind == kInFar ? 1 - in_index : c->far_in;
+  const int so = c->spill_out;
+  const unsigned spill_raw = ld(&c->spill_tail[so]);
+  const unsigned far_raw = ld(&c->far_tail[far_in]);
+  const unsigned fmin = far_raw ? ld(&c->far_min[far_in]) : kNoBucket;
+  // window occupancy, lane j looks at bucket cur + j
+  unsigned wraw = 0;
+  bool nonempty = false;
+  if (lane < K) {
+    const unsigned slot = (cur + (unsigned)lane) & (unsigned)(K - 1);
+    const bool consumed = in_kind == kInWin && (int)slot == in_index;
+    wraw = consumed ? 0u : ld(&c->win_tail[slot]);
+    const unsigned bk = cur + (unsigned)lane;
+    nonempty = wraw > 0 && bk >= cur && bk < c->win_hi;
+  }
+  unsigned long long need_w = wraw;
+  for (int o = 32; o >= 1; o >>= 1) {
+    unsigned long long y = __shfl_xor(need_w, o);
+    need_w = need_w > y ? need_w : y;
+  }
+  const unsigned slot_cur_cnt = __shfl(wraw, 0);
+  const unsigned long long ne = __ballot(nonempty) & ~1ull;  // buckets after cur
+  if (lane != 0) return;
+  // the consumed input list is empty again
+  if (in_kind == kInWin) c->win_tail[in_index] = 0;
+  else if (in_kind == kInSpill) c->spill_tail[in_index] = 0;
+  else {
+    c->far_tail[in_index] = 0;
+    c->far_min[in_index] = kNoBucket;
+  }
+
+  unsigned long long need = c->need;
+  if (need_w > need) need = need_w;
+  if (spill_raw > need) need = spill_raw;
+  if (far_raw > need) need = far_raw;
+  c->need = need;
+
+  auto clampcap = [&](unsigned x) { return x < a.cap ? x : a.cap; };
+  int done = 0;
+  unsigned ncur = cur, count = 0, buckets = c->buckets;
+  int nkind = kInWin, nindex = 0, nspill_out = so;
+  if (status != 0) {
+    done = 1;
+  } else if (a.max_rounds && round >= a.max_rounds) {
+    status = OG_ERR_ROUND_LIMIT;
+    c->status = status;
+    done = 1;
+  } else if (far_raw && fmin <= cur) {
+    nkind = kInFar;
+    nindex = far_in;
+    count = clampcap(far_raw);
+  } else if (slot_cur_cnt) {
+    nkind = kInWin;
+    nindex = (int)(cur & (unsigned)(K - 1));
+    count = clampcap(slot_cur_cnt);
+  } else if (spill_raw) {
+    nkind = kInSpill;
+    nindex = so;
+    nspill_out = 1 - so;
+    count = clampcap(spill_raw);
+  } else {
+    const unsigned wnext = ne ? cur + (unsigned)(__ffsll((long long)ne) - 1) : kNoBucket;
+    const unsigned next = wnext < fmin ? wnext : fmin;
+    if (next == kNoBucket) {
+      done = 1;
+    } else {
+      if (a.target >= 0) {
+        const int dt = __hip_atomic_load(&a.dist[a.target], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (dt != kInf && (unsigned long long)next * a.delta >= (unsigned long long)dt) done = 1;
+      }
+      if (!done) {
+        ncur = next;
+        buckets++;
+        if (fmin == next) {
+          nkind = kInFar;
+          nindex = far_in;
+          count = clampcap(far_raw);
+        } else {
+          nkind = kInWin;
+          nindex = (int)(next & (unsigned)(K - 1));
+          count = clampcap(ld(&c->win_tail[nindex]));
+        }
+        c->win_hi = sat_add(next, (unsigned)K);
+      }
+    }
+  }
+  unsigned chunk = (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg;
+  if (chunk < 1) chunk = 1;
+  if (chunk > (unsigned)kBlock) chunk = kBlock;
+  c->cur = ncur;
+  c->in_kind = nkind;
+  c->in_index = nindex;
+  c->in_count = count;
+  c->in_head = 0;
+  c->chunk = chunk;
+  c->spill_out = nspill_out;
+  c->far_in = far_in;
+  c->round = round;
+  c->buckets = buckets;
+  c->done = done;
+}
+
+__device__ void load_control(const Args& a, Smem& s) {
+  Ctl* c = a.ctl;
+  s.cur = c->cur;
+  s.in_kind = c->in_kind;
+  s.in_index = c->in_index;
+  s.in_count = c->in_count;
+  s.chunk = c->chunk;
+  s.win_hi = c->win_hi;
+  s.spill_out = c->spill_out;
+  s.far_out = s.in_kind == kInFar ? 1 - c->far_in : c->far_in;
+  s.done = c->done || c->status != 0;
+}
+
+__device__ void flush_counters(const Args& a, const Counters& c) {
+  unsigned long long v[5] = {c.relax, c.improve, c.push_local, c.push_global, c.far};
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+    for (int o = 32; o >= 1; o >>= 1) v[i] += __shfl_xor(v[i], o);
+  if (lane_id() == 0) {
+    Ctl* ctl = a.ctl;
+    if (v[0]) atomicAdd(&ctl->st_relax, v[0]);
+    if (v[1]) atomicAdd(&ctl->st_improve, v[1]);
+    if (v[2]) atomicAdd(&ctl->st_push_local, v[2]);
+    if (v[3]) atomicAdd(&ctl->st_push_global, v[3]);
+    if (v[4]) atomicAdd(&ctl->st_far, v[4]);
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(kBlock) void k_init(Args a, int src) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride)
+    a.dist[v] = v == src ? 0 : kInf;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl* c = a.ctl;
+    unsigned* words = reinterpret_cast<unsigned*>(c);
+    for (size_t i = 0; i < sizeof(Ctl) / sizeof(unsigned); ++i) words[i] = 0;
+    const unsigned b0 = bucket_of(a, src, 0u);
+    const int slot = (int)(b0 & (unsigned)(a.K - 1));
+    c->cur = b0;
+    c->in_kind = kInWin;
+    c->in_index = slot;
+    c->in_count = 1;
+    c->chunk = 1;
+    c->win_tail[slot] = 1;
+    c->win_hi = sat_add(b0, (unsigned)a.K);
+    c->far_min[0] = c->far_min[1] = kNoBucket;
+    c->buckets = 1;
+    c->need = 1;
+    a.win[(size_t)slot * a.cap] = make_int2(src, 0);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate(const int* w, long long m, Ctl* ctl) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) bad |= w[e] < 0;
+  if (__ballot(bad) && lane_id() == 0) atomicExch(&ctl->status, OG_ERR_NEGATIVE_WEIGHT);
+}
+
+// End-of-round synchronisation across the whole grid.  Every wavefront
+// releases its global writes at device (agent) scope, thread 0 of each
+// workgroup arrives on a device-wide counter, and the last workgroup to
+// arrive runs the bucket decision with wave 0.  With wait_others (the
+// persistent engine) every other workgroup then spins on the barrier
+// generation until the decision is published and acquires it; the
+// host-driven engine instead ends the kernel.  Returns true if this
+// workgroup ran the decision.
+__device__ bool round_barrier(const Args& a, Smem& s, bool wait_others) {
+  Ctl* ctl = a.ctl;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s.gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned prev =
+        __hip_atomic_fetch_add(&ctl->bar_arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s.last = prev == (unsigned)a.nwg - 1;
+  }
+  __syncthreads();
+  const bool last = s.last;
+  if (last) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x < kWave) decide(a);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&ctl->bar_arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->bar_gen, s.gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (wait_others && threadIdx.x == 0) {
+    const unsigned gen = s.gen;
+    while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+      __builtin_amdgcn_s_sleep(1);
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
+}
+
+// Persistent engine: one cooperative launch; rounds separated by a
+// device-wide barrier whose last arriver takes the bucket decision.
+__global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
+  __shared__ Smem s;
+  Counters c;
+  if (threadIdx.x == 0) load_control(a, s);
+  __syncthreads();
+  while (!s.done) {
+    run_round(a, s, c);
+    round_barrier(a, s, true);
+    if (threadIdx.x == 0) load_control(a, s);
+    __syncthreads();
+  }
+  flush_counters(a, c);
+}
+
+// Host-driven engine: one launch per round; the last workgroup to finish
+// takes the bucket decision for the next launch.
+__global__ __launch_bounds__(kBlock) void k_round(Args a) {
+  __shared__ Smem s;
+  Counters c;
+  if (threadIdx.x == 0) load_control(a, s);
+  __syncthreads();
+  if (s.done) return;
+  run_round(a, s, c);
+  round_barrier(a, s, false);
+  flush_counters(a, c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int* p, int n, int value) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) p[v] = value;
+}
+
+// Canonical predecessors: for every edge (u,v) with dist[u] finite and
+// dist[u] + w == dist[v], pred[v] = min(pred[v], u).  One wavefront per
+// chunk of 64 consecutive source vertices walks the chunk's contiguous edge
+// range with coalesced loads; each edge finds its source lane by a binary
+// search over the lanes' row offsets.  Also counts reached vertices/edges.
+// pred == nullptr: counts only.
+__global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
+  const int lane = (int)lane_id();
+  const long long nwave = (long long)gridDim.x * (kBlock / kWave);
+  unsigned long long rv = 0, re = 0;
+  for (long long ch = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; ch * kWave < a.n;
+       ch += nwave) {
+    const long long v0 = ch * kWave;
+    const long long v = v0 + lane;
+    const long long vend = v0 + kWave < a.n ? v0 + kWave : a.n;
+    const long long e0 = a.row_ptr[v0];
+    const long long e1 = a.row_ptr[vend];
+    const int rs = v < a.n ? (int)(a.row_ptr[v] - e0) : (int)(e1 - e0);
+    const int dv = v < a.n ? a.dist[v] : kInf;
+    if (v < a.n && dv != kInf) {
+      rv++;
+      re += (unsigned long long)(a.row_ptr[v + 1] - a.row_ptr[v]);
+    }
+    if (!pred) continue;
+    for (long long base = e0; base < e1; base += kWave) {
+      const long long e = base + lane;
+      const int rel = (int)(e - e0);
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int r = __shfl(rs, lo + step);
+        if (r <= rel) lo += step;
+      }
+      const int du = __shfl(dv, lo);
+      if (e < e1 && du != kInf) {
+        const int u = a.col[e];
+        const unsigned nd = (unsigned)du + (unsigned)a.w[e];
+        if (nd == (unsigned)a.dist[u]) atomicMin(&pred[u], (int)(v0 + lo));
+      }
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    rv += __shfl_xor(rv, o);
+    re += __shfl_xor(re, o);
+  }
+  if (lane == 0) {
+    if (rv) atomicAdd(&a.ctl->st_reached_v, rv);
+    if (re) atomicAdd(&a.ctl->st_reached_e, re);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pred_fix(int* pred, int n, int src) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    if (v == src) pred[v] = src;
+    else if (pred[v] == kInf) pred[v] = -1;
+  }
+}
+
+// ------------------------------------------------------------------ host
+
+struct DeviceInfo {
+  int cus = 0;
+  int occ_persistent = 0;
+  int coop = 0;
+  bool valid = false;
+};
+
+std::mutex g_info_mu;
+DeviceInfo g_info[64];
+
+bool device_info(int dev, DeviceInfo* out) {
+  if (dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lk(g_info_mu);
+  DeviceInfo& di = g_info[dev];
+  if (!di.valid) {
+    if (hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&di.coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_persistent, k_persistent, kBlock, 0) !=
+        hipSuccess)
+      return false;
+    di.valid = true;
+  }
+  *out = di;
+  return true;
+}
+
+int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+og_schedule resolved(const og_schedule* s) {
+  og_schedule r = *s;
+  if (r.update != OG_EAGER_NO_FUSION) r.update = OG_EAGER_WITH_FUSION;
+  if (r.fusion_threshold <= 0) r.fusion_threshold = kDefaultThreshold;
+  if (r.fusion_threshold > kLq) r.fusion_threshold = kLq;
+  if (r.window_buckets <= 0) r.window_buckets = kDefaultK;
+  r.window_buckets = pow2_at_least(r.window_buckets < 2 ? 2 : r.window_buckets);
+  return r;
+}
+
+long long queue_cap(const og_graph* g, const og_schedule* r) {
+  long long cap = r->queue_capacity > 0 ? r->queue_capacity : (long long)g->n + g->m / 8;
+  if (cap < 1024) cap = 1024;
+  if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+  return cap;
+}
+
+size_t ws_bytes_for(const og_graph* g, const og_schedule* r) {
+  const long long cap = queue_cap(g, r);
+  const size_t lists = (size_t)r->window_buckets + 4;  // K window slots, 2 spill, 2 far
+  size_t b = kCtlBytes + lists * (size_t)cap * sizeof(int2);
+  return (b + 255) & ~(size_t)255;
+}
+
+bool schedule_ok(const og_schedule* s) {
+  if (!s) return false;
+  if (s->delta < 1) return false;
+  if (s->update != OG_EAGER_NO_FUSION && s->update != OG_EAGER_WITH_FUSION) return false;
+  if (s->fusion_threshold < 0 || s->window_buckets < 0 || s->window_buckets > kKmax) return false;
+  if (s->window_buckets == 1) return false;
+  if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS) return false;
+  if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
+  if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC)) return false;
+  return true;
+}
+
+bool graph_ok(const og_graph* g) {
+  if (!g || g->n < 1 || g->m < 0 || g->m > 0x7fffffffLL || !g->row_ptr) return false;
+  if (g->m > 0 && (!g->col || !g->w)) return false;
+  return true;
+}
+
+void fill_stats(const Ctl& h, og_stats* st, int nwg) {
+  if (!st) return;
+  st->status = h.status;
+  st->workgroups = nwg;
+  st->rounds = h.round;
+  st->buckets = h.buckets;
+  st->relaxations = (int64_t)h.st_relax;
+  st->improvements = (int64_t)h.st_improve;
+  st->pushes_local = (int64_t)h.st_push_local;
+  st->pushes_global = (int64_t)h.st_push_global;
+  st->far_pushes = (int64_t)h.st_far;
+  st->reached_vertices = (int64_t)h.st_reached_v;
+  st->reached_edges = (int64_t)h.st_reached_e;
+  st->queue_needed = (int64_t)h.need;
+}
+
+og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, const og_schedule* sched,
+              int32_t* dist, int32_t* pred, void* ws, size_t ws_size, og_stats* stats, void* stream_v,
+              bool force_delta1) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  auto fail = [&](og_status st) {
+    if (stats) stats->status = st;
+    return st;
+  };
+  if (!graph_ok(g) || !schedule_ok(sched) || !dist || !ws) return fail(OG_ERR_INVALID_ARG);
+  if (src < 0 || src >= g->n) return fail(OG_ERR_INVALID_ARG);
+  if (dst != -1 && (dst < 0 || dst >= g->n)) return fail(OG_ERR_INVALID_ARG);
+  if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
+  og_schedule r = resolved(sched);
+  if (force_delta1) r.delta = 1;
+  if (ws_size < ws_bytes_for(g, &r)) {
+    if (stats) stats->queue_needed = 0;
+    return fail(OG_ERR_WORKSPACE);
+  }
+  hipStream_t stream = (hipStream_t)stream_v;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(OG_ERR_HIP);
+  DeviceInfo di;
+  if (!device_info(dev, &di)) return fail(OG_ERR_HIP);
+  const bool persistent = r.engine == OG_ENGINE_PERSISTENT;
+  if (persistent && !di.coop) return fail(OG_ERR_HIP);
+  int maxwg = di.cus * (di.occ_persistent > 0 ? di.occ_persistent : 1);
+  int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
+  if (persistent && nwg > maxwg) nwg = maxwg;
+  if (nwg < 1) nwg = 1;
+
+  const long long cap = queue_cap(g, &r);
+  char* base = (char*)ws;
+  Args a;
+  a.row_ptr = (const long long*)g->row_ptr;
+  a.col = g->col;
+  a.w = g->w;
+  a.dist = dist;
+  a.h = h;
+  a.n = g->n;
+  a.target = dst;
+  a.delta = (unsigned)r.delta;
+  a.shift = -1;
+  if ((r.delta & (r.delta - 1)) == 0) {
+    int sh = 0;
+    while ((1 << sh) < r.delta) sh++;
+    a.shift = sh;
+  }
+  a.K = r.window_buckets;
+  a.cap = (unsigned)cap;
+  a.fused = r.update == OG_EAGER_WITH_FUSION;
+  a.threshold = (unsigned)r.fusion_threshold;
+  a.max_rounds = (unsigned)r.max_rounds;
+  a.nwg = nwg;
+  a.ctl = (Ctl*)base;
+  a.win = (int2*)(base + kCtlBytes);
+  a.spill = a.win + (size_t)a.K * (size_t)cap;
+  a.far = a.spill + 2 * (size_t)cap;
+
+  const int fill_grid = di.cus * 8;
+  hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, src);
+  if (r.flags & OG_FLAG_VALIDATE)
+    hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
+  if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
+
+  if (persistent) {
+    void* kargs[] = {&a};
+    if (hipLaunchCooperativeKernel((const void*)k_persistent, dim3(nwg), dim3(kBlock), kargs, 0, stream) !=
+        hipSuccess)
+      return fail(OG_ERR_HIP);
+  } else {
+    // Launch rounds in groups and poll the done flag between groups; a
+    // launch after completion returns at once.
+    const int group = 32;
+    int done = 0;
+    long long launched = 0;
+    const long long cap_launches = r.max_rounds > 0 ? (long long)r.max_rounds + group : (1LL << 40);
+    while (!done && launched < cap_launches) {
+      for (int i = 0; i < group; ++i) hipLaunchKernelGGL(k_round, dim3(nwg), dim3(kBlock), 0, stream, a);
+      launched += group;
+      int hd[2];
+      if (hipMemcpyAsync(hd, &a.ctl->done, sizeof(int) * 2, hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return fail(OG_ERR_HIP);
+      if (hipStreamSynchronize(stream) != hipSuccess) return fail(OG_ERR_HIP);
+      done = hd[0] || hd[1];
+    }
+  }
+  if (pred) {
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, g->n, kInf);
+    hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
+    hipLaunchKernelGGL(k_pred_fix, dim3(fill_grid), dim3(kBlock), 0, stream, pred, g->n, src);
+  } else if (stats) {
+    hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
+  if (r.flags & OG_FLAG_ASYNC) {
+    if (stats) stats->workgroups = nwg;
+    return OG_OK;
+  }
+  Ctl hc;
+  if (hipMemcpyAsync(&hc, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return fail(OG_ERR_HIP);
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(OG_ERR_HIP);
+  fill_stats(hc, stats, nwg);
+  return hc.status;
+}
+
+}  // namespace og
+
+extern "C" {
+
+int32_t og_version(void) { return (1 << 16) | 0; }
+
+const char* og_status_string(og_status s) {
+  switch (s) {
+    case OG_OK: return "ok";
+    case OG_ERR_INVALID_ARG: return "invalid argument";
+    case OG_ERR_NEGATIVE_WEIGHT: return "negative edge weight";
+    case OG_ERR_OVERFLOW: return "path length overflows int32";
+    case OG_ERR_WORKSPACE: return "workspace too small or a queue overflowed";
+    case OG_ERR_HIP: return "HIP runtime error";
+    case OG_ERR_ROUND_LIMIT: return "round limit reached";
+    default: return "unknown status";
+  }
+}
+
+og_status og_default_schedule(og_schedule* s) {
+  if (!s) return OG_ERR_INVALID_ARG;
+  std::memset(s, 0, sizeof(*s));
+  s->delta = 1;
+  s->update = OG_EAGER_WITH_FUSION;
+  s->fusion_threshold = og::kDefaultThreshold;
+  s->window_buckets = og::kDefaultK;
+  s->engine = OG_ENGINE_PERSISTENT;
+  return OG_OK;
+}
+
+size_t og_workspace_bytes(const og_graph* g, const og_schedule* s) {
+  if (!og::graph_ok(g) || !og::schedule_ok(s)) return 0;
+  og_schedule r = og::resolved(s);
+  return og::ws_bytes_for(g, &r);
+}
+
+og_status og_sssp(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
+                  void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
+  return og::run(g, src, -1, nullptr, s, dist, pred, ws, ws_bytes, stats, stream, false);
+}
+
+og_status og_wbfs(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
+                  void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
+  return og::run(g, src, -1, nullptr, s, dist, pred, ws, ws_bytes, stats, stream, true);
+}
+
+og_status og_ppsp(const og_graph* g, int32_t src, int32_t dst, const og_schedule* s, int32_t* dist,
+                  int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
+  if (dst < 0) {
+    if (stats) std::memset(stats, 0, sizeof(*stats)), stats->status = OG_ERR_INVALID_ARG;
+    return OG_ERR_INVALID_ARG;
+  }
+  return og::run(g, src, dst, nullptr, s, dist, pred, ws, ws_bytes, stats, stream, false);
+}
+
+og_status og_astar(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, const og_schedule* s,
+                   int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
+  if (dst < 0 || !h) {
+    if (stats) std::memset(stats, 0, sizeof(*stats)), stats->status = OG_ERR_INVALID_ARG;
+    return OG_ERR_INVALID_ARG;
+  }
+  return og::run(g, src, dst, h, s, dist, pred, ws, ws_bytes, stats, stream, false);
+}
+
+og_status og_read_stats(const void* ws, og_stats* stats, void* stream) {
+  if (!ws || !stats) return OG_ERR_INVALID_ARG;
+  og::Ctl hc;
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(&hc, ws, sizeof(og::Ctl), hipMemcpyDeviceToHost, st) != hipSuccess) return OG_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return OG_ERR_HIP;
+  const int wg = stats->workgroups;
+  og::fill_stats(hc, stats, wg);
+  return hc.status;
+}
+
+}  // extern "C"

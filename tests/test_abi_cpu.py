@@ -1,0 +1,134 @@
+"""C ABI checks that need no GPU: every symbol declared in include/*.h is
+exported by libog.so, struct layouts agree with the header, and argument
+validation rejects bad calls before anything is launched."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+import paper_1911_07260_amd as og
+from paper_1911_07260_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(og_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib.load()
+    names = declared_functions()
+    assert "og_sssp" in names and "og_astar" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+
+
+def test_no_oracle_in_product():
+    """The product library links no oracle code and the package never
+    imports it."""
+    src = open(os.path.join(ROOT, "paper_1911_07260_amd", "csrc", "og_engine.hip")).read()
+    assert "oracle" not in src
+    for py in glob.glob(os.path.join(ROOT, "paper_1911_07260_amd", "*.py")):
+        assert "import oracle" not in open(py).read()
+    lib = _lib.load()
+    assert not hasattr(lib, "oracle_dijkstra")
+
+
+def test_version_and_strings():
+    assert og.version() >> 16 == 1
+    assert og.status_string(0) == "ok"
+    assert "workspace" in og.status_string(og.OG_ERR_WORKSPACE)
+    assert og.status_string(12345) == "unknown status"
+
+
+def test_default_schedule():
+    lib = _lib.load()
+    s = _lib.OgSchedule()
+    assert lib.og_default_schedule(ctypes.byref(s)) == 0
+    assert s.delta == 1 and s.update == 1 and s.window_buckets == 16 and s.fusion_threshold == 1024
+    assert lib.og_default_schedule(None) == og.OG_ERR_INVALID_ARG
+
+
+def _fake_graph(n=10, m=20):
+    # never dereferenced: these calls must fail validation first
+    return _lib.OgGraph(n, m, 0x1000, 0x2000, 0x3000)
+
+
+def test_workspace_bytes():
+    lib = _lib.load()
+    g = _fake_graph(1000, 4000)
+    s = og.Schedule(delta=4).to_c()
+    b = lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s))
+    assert b % 256 == 0 and b >= 4096 + (16 + 4) * 1024 * 8
+    s2 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000).to_c()
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 4096 + 12 * 5000 * 8
+    bad = og.Schedule(delta=0).to_c()
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
+    g0 = _lib.OgGraph(0, 0, 0x1000, None, None)
+    assert lib.og_workspace_bytes(ctypes.byref(g0), ctypes.byref(s)) == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("delta", 0), ("update", 2), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
+    ("max_rounds", -1), ("flags", 8), ("fusion_threshold", -2),
+])
+def test_invalid_schedule_rejected(field, value):
+    lib = _lib.load()
+    g = _fake_graph()
+    s = og.Schedule(delta=4)
+    setattr(s, field, value)
+    sc = s.to_c()
+    st = _lib.OgStats()
+    rc = lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), ctypes.c_void_p(0x4000), None,
+                     ctypes.c_void_p(0x10000), ctypes.c_size_t(1 << 40), ctypes.byref(st), None)
+    assert rc == og.OG_ERR_INVALID_ARG and st.status == rc
+
+
+def test_invalid_calls_rejected():
+    lib = _lib.load()
+    g = _fake_graph()
+    sc = og.Schedule(delta=4).to_c()
+    st = _lib.OgStats()
+    ws = ctypes.c_void_p(0x10000)
+    big = ctypes.c_size_t(1 << 40)
+    d = ctypes.c_void_p(0x4000)
+    E = og.OG_ERR_INVALID_ARG
+    assert lib.og_sssp(ctypes.byref(g), -1, ctypes.byref(sc), d, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_sssp(ctypes.byref(g), 10, ctypes.byref(sc), d, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_sssp(None, 0, ctypes.byref(sc), d, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_sssp(ctypes.byref(g), 0, None, d, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), None, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), d, None, None, big, ctypes.byref(st), None) == E
+    # misaligned workspace
+    assert lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), d, None, ctypes.c_void_p(0x10008), big,
+                       ctypes.byref(st), None) == E
+    # ppsp / astar targets and estimate
+    assert lib.og_ppsp(ctypes.byref(g), 0, 10, ctypes.byref(sc), d, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_ppsp(ctypes.byref(g), 0, -1, ctypes.byref(sc), d, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_astar(ctypes.byref(g), 0, 3, None, ctypes.byref(sc), d, None, ws, big, ctypes.byref(st),
+                        None) == E
+    # bad graphs
+    for bad in (_lib.OgGraph(5, 3, None, 0x1, 0x1), _lib.OgGraph(5, 3, 0x1, None, 0x1),
+                _lib.OgGraph(5, -1, 0x1, 0x1, 0x1), _lib.OgGraph(5, 1 << 31, 0x1, 0x1, 0x1)):
+        assert lib.og_sssp(ctypes.byref(bad), 0, ctypes.byref(sc), d, None, ws, big, ctypes.byref(st),
+                           None) == E
+
+
+def test_workspace_too_small():
+    lib = _lib.load()
+    g = _fake_graph()
+    sc = og.Schedule(delta=4).to_c()
+    st = _lib.OgStats()
+    need = lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(sc))
+    rc = lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), ctypes.c_void_p(0x4000), None,
+                     ctypes.c_void_p(0x10000), ctypes.c_size_t(need - 256), ctypes.byref(st), None)
+    assert rc == og.OG_ERR_WORKSPACE
