@@ -28,9 +28,9 @@
  *     for the stream before returning and reports the device-side status.
  *   - Graphs are directed CSR: the out-edges of v are col[row_ptr[v] ..
  *     row_ptr[v+1]) with weights w[...].  An undirected graph stores both
- *     directions.  Weights are int32 >= 0; a negative weight is reported as
- *     OG_ERR_NEGATIVE_WEIGHT when OG_FLAG_VALIDATE is set and otherwise makes
- *     the result undefined (it surfaces as OG_ERR_OVERFLOW).
+ *     directions.  Weights are int32 >= 0.  A negative weight on an edge the
+ *     search examines is reported as OG_ERR_NEGATIVE_WEIGHT (outputs then
+ *     undefined); OG_FLAG_VALIDATE checks every weight before running.
  *   - Distances are int32 with INF = INT32_MAX for unreachable vertices.  A
  *     finite path length that does not fit below INT32_MAX is reported as
  *     OG_ERR_OVERFLOW (the outputs are then undefined).
@@ -53,7 +53,7 @@ extern "C" {
 typedef int32_t og_status;
 #define OG_OK 0
 #define OG_ERR_INVALID_ARG (-1)     /* bad argument; nothing was launched       */
-#define OG_ERR_NEGATIVE_WEIGHT (-2) /* OG_FLAG_VALIDATE found a weight < 0      */
+#define OG_ERR_NEGATIVE_WEIGHT (-2) /* an edge weight < 0 was found             */
 #define OG_ERR_OVERFLOW (-3)        /* a path length reached INT32_MAX          */
 #define OG_ERR_WORKSPACE (-4)       /* ws_bytes too small, or a queue filled up;
                                        og_stats.queue_needed tells how many
@@ -65,6 +65,8 @@ typedef int32_t og_status;
 #define OG_FLAG_VALIDATE 1u /* scan weights for negatives before running      */
 #define OG_FLAG_ASYNC 2u    /* do not wait; read the status later with
                                og_read_stats() after synchronising the stream */
+#define OG_FLAG_TIMING 4u   /* time the phases with HIP events recorded on the
+                               stream (ignored with OG_FLAG_ASYNC)            */
 
 /* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
 #define OG_EAGER_NO_FUSION 0
@@ -116,6 +118,9 @@ typedef struct og_stats {
   int64_t reached_vertices; /* dist < INF (computed when pred or stats given) */
   int64_t reached_edges;    /* sum of out-degrees of reached vertices         */
   int64_t queue_needed;     /* largest queue fill requested, in entries       */
+  double init_ms;           /* OG_FLAG_TIMING: initialisation kernel          */
+  double engine_ms;         /* OG_FLAG_TIMING: bucket engine (all rounds)     */
+  double pred_ms;           /* OG_FLAG_TIMING: predecessor / counting pass    */
 } og_stats;
 
 /* Library version, (major << 16) | minor. */
@@ -124,8 +129,8 @@ int32_t og_version(void);
 /* Human-readable name of a status code (static string). */
 const char* og_status_string(og_status s);
 
-/* Fills *s with the defaults (delta = 1 unless set by the caller before the
- * call is irrelevant: every field is overwritten). */
+/* Overwrites every field of *s with the defaults (delta 1, fusion on,
+ * threshold 1024, 16 window buckets, persistent engine, no limits). */
 og_status og_default_schedule(og_schedule* s);
 
 /* Workspace bytes og_sssp & co. need for this graph and schedule (0 if the

@@ -22,6 +22,7 @@ OG_ERR_ROUND_LIMIT = -6
 
 OG_FLAG_VALIDATE = 1
 OG_FLAG_ASYNC = 2
+OG_FLAG_TIMING = 4
 
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1
@@ -68,10 +69,14 @@ class OgStats(ctypes.Structure):
         ("reached_vertices", ctypes.c_int64),
         ("reached_edges", ctypes.c_int64),
         ("queue_needed", ctypes.c_int64),
+        ("init_ms", ctypes.c_double),
+        ("engine_ms", ctypes.c_double),
+        ("pred_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+        return {name: (float(getattr(self, name)) if name.endswith("_ms") else int(getattr(self, name)))
+                for name, _ in self._fields_}
 
 
 class OgError(RuntimeError):

@@ -759,6 +759,20 @@ int pow2_at_least(int x) {
   return p;
 }
 
+// Per-thread HIP events for OG_FLAG_TIMING (created on first use).
+struct Timers {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ok = false;
+  bool init() {
+    if (ok) return true;
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) return false;
+    ok = true;
+    return true;
+  }
+};
+thread_local Timers t_timers;
+
 og_schedule resolved(const og_schedule* s) {
   og_schedule r = *s;
   if (r.update != OG_EAGER_NO_FUSION) r.update = OG_EAGER_WITH_FUSION;
@@ -791,7 +805,7 @@ bool schedule_ok(const og_schedule* s) {
   if (s->window_buckets == 1) return false;
   if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS) return false;
   if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
-  if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC)) return false;
+  if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING)) return false;
   return true;
 }
 
@@ -875,11 +889,14 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   a.spill = a.win + (size_t)a.K * (size_t)cap;
   a.far = a.spill + 2 * (size_t)cap;
 
+  const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
+  if (timing) hipEventRecord(t_timers.ev[0], stream);
   const int fill_grid = di.cus * 8;
   hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, src);
   if (r.flags & OG_FLAG_VALIDATE)
     hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
+  if (timing) hipEventRecord(t_timers.ev[1], stream);
 
   if (persistent) {
     void* kargs[] = {&a};
@@ -903,6 +920,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
       done = hd[0] || hd[1];
     }
   }
+  if (timing) hipEventRecord(t_timers.ev[2], stream);
   if (pred) {
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, g->n, kInf);
     hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
@@ -910,6 +928,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   } else if (stats) {
     hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
   }
+  if (timing) hipEventRecord(t_timers.ev[3], stream);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
   if (r.flags & OG_FLAG_ASYNC) {
     if (stats) stats->workgroups = nwg;
@@ -920,6 +939,12 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
     return fail(OG_ERR_HIP);
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(OG_ERR_HIP);
   fill_stats(hc, stats, nwg);
+  if (timing && stats) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t_timers.ev[0], t_timers.ev[1]) == hipSuccess) stats->init_ms = ms;
+    if (hipEventElapsedTime(&ms, t_timers.ev[1], t_timers.ev[2]) == hipSuccess) stats->engine_ms = ms;
+    if (hipEventElapsedTime(&ms, t_timers.ev[2], t_timers.ev[3]) == hipSuccess) stats->pred_ms = ms;
+  }
   return hc.status;
 }
 
