@@ -45,37 +45,53 @@ constexpr int kLq = 2048;  // LDS ring entries (power of two)
 constexpr int kKmax = 64;
 constexpr int kDefaultK = 16;
 constexpr int kDefaultThreshold = 1024;
-constexpr size_t kCtlBytes = 4096;
+constexpr int kGroup = 16;   // workgroups per first-level barrier counter
+constexpr int kMaxWg = 4096;
+constexpr int kMaxGroups = kMaxWg / kGroup;
+constexpr int kFlags = 64;   // release flags, one per 128-byte line
+constexpr size_t kCtlBytes = 65536;
 constexpr unsigned kNoBucket = 0xffffffffu;
 constexpr int kInf = INT_MAX;
 
 enum : int { kInWin = 0, kInSpill = 1, kInFar = 2 };
+enum : int { kStRelax, kStImprove, kStPushLocal, kStPushGlobal, kStFar, kStReachedV, kStReachedE, kStCount };
+
+// Every counter that many workgroups update sits on its own 128-byte line.
+struct alignas(128) Word {
+  unsigned v;
+};
+struct alignas(128) Word64 {
+  unsigned long long v;
+};
+
+// State chosen by the bucket decision for the next round.
+struct alignas(128) Control {
+  unsigned cur;       // current bucket
+  unsigned in_kind;   // round input: window slot / spill list / far list
+  unsigned in_index;
+  unsigned in_count;
+  unsigned done;
+  unsigned spill_out;  // spill list receiving current-bucket pushes
+  unsigned far_in;     // far list holding pending overflow entries
+  unsigned win_hi;     // buckets >= win_hi go to the far list
+  unsigned round;
+  unsigned buckets;
+};
 
 // Device-side control block at the start of the workspace.
 struct Ctl {
-  unsigned bar_arrive;  // barrier arrivals in the current round
-  unsigned bar_gen;     // barrier generation
-  unsigned cur;         // current bucket
-  int in_kind;          // round input: window slot / spill list / far list
-  int in_index;
-  unsigned in_count;
-  unsigned in_head;  // dynamic chunk cursor into the round input
-  unsigned chunk;
-  int done;
-  int status;
-  int spill_out;  // spill list receiving current-bucket pushes this round
-  int far_in;     // far list holding pending overflow entries
-  unsigned win_hi;  // buckets >= win_hi go to the far list
-  unsigned round;
-  unsigned buckets;
-  unsigned pad0;
-  unsigned win_tail[kKmax];
-  unsigned spill_tail[2];
-  unsigned far_tail[2];
-  unsigned far_min[2];
-  unsigned long long need;
-  unsigned long long st_relax, st_improve, st_push_local, st_push_global, st_far;
-  unsigned long long st_reached_v, st_reached_e;
+  Control c;
+  Word status;
+  Word in_head;  // dynamic chunk cursor into a large round input
+  Word bar_root;
+  Word bar_grp[kMaxGroups];
+  Word flag[kFlags];  // release flags: the round number now allowed to start
+  Word win_tail[kKmax];
+  Word spill_tail[2];
+  Word far_tail[2];
+  Word far_min[2];
+  Word64 need;
+  Word64 st[kStCount];
 };
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block too large");
 
@@ -117,20 +133,42 @@ struct Smem {
   int exhausted;
   int last;
   int tbound;
-  unsigned gen;
   // snapshot of the control block for this round
-  unsigned cur, in_count, chunk, win_hi;
+  unsigned cur, in_count, win_hi, round;
   int in_kind, in_index, done, spill_out, far_out;
 };
 
-__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
-__device__ __forceinline__ unsigned long long lanemask_lt() {
-  return (1ull << lane_id()) - 1ull;
+// ------------------------------------------------- device-coherent access
+// Data that one workgroup writes and another reads in a later round goes
+// through device-scope (write-through / cache-bypassing) stores and loads,
+// so a round boundary needs no cache write-back or invalidation: only the
+// writer's completion wait before it arrives at the barrier.
+__device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int2 ld_entry(const int2* q, size_t i) {
+  const unsigned long long x =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(q + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_int2((int)(unsigned)(x & 0xffffffffull), (int)(unsigned)(x >> 32));
+}
+__device__ __forceinline__ void st_entry(int2* q, size_t i, int v, int d) {
+  const unsigned long long x = (unsigned long long)(unsigned)v | ((unsigned long long)(unsigned)d << 32);
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(q + i), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until this wavefront's vector memory operations (stores and
+// atomics included) have completed; also a compiler memory barrier.
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-__device__ __forceinline__ unsigned bucket_of(const Args& a, int v, unsigned d) {
-  unsigned key = d;
-  if (a.h) key += (unsigned)a.h[v];  // both < 2^31: no wrap
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+__device__ __forceinline__ unsigned long long lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ unsigned bucket_key(const Args& a, int v, unsigned d) {
+  return a.h ? d + (unsigned)a.h[v] : d;  // both < 2^31: no wrap
+}
+__device__ __forceinline__ unsigned bucket_of_key(const Args& a, unsigned key) {
   return a.shift >= 0 ? (key >> a.shift) : (key / a.delta);
 }
 
@@ -138,7 +176,9 @@ __device__ __forceinline__ unsigned sat_add(unsigned x, unsigned y) {
   return x > 0xffffffffu - y ? 0xffffffffu : x + y;
 }
 
-__device__ __forceinline__ void set_status(Ctl* c, int st) { atomicCAS(&c->status, 0, st); }
+__device__ __forceinline__ void set_status(Ctl* c, int st) {
+  atomicCAS(reinterpret_cast<int*>(&c->status.v), 0, st);
+}
 
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
   int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
@@ -170,8 +210,9 @@ __device__ int block_excl_scan(int x, Smem& s, int* total) {
 
 // Wave-cooperative append of (v, d) entries to global queues.  Targets:
 // 0..K-1 window slots, K = this round's spill list, K+1 = far list.  All 64
-// lanes must call it together.  A full window slot or spill list falls back
-// to the far list; a full far list sets OG_ERR_WORKSPACE and drops the entry.
+// lanes must call it together.  One atomic per wavefront and target reserves
+// the slots.  A full window slot or spill list falls back to the far list;
+// a full far list sets OG_ERR_WORKSPACE and drops the entry.
 __device__ void wave_push_global(const Args& a, const Smem& s, Counters& c, bool has, int tgt, int v,
                                  int d, unsigned b) {
   Ctl* ctl = a.ctl;
@@ -186,13 +227,13 @@ __device__ void wave_push_global(const Args& a, const Smem& s, Counters& c, bool
     unsigned* tail;
     int2* q;
     if (t < K) {
-      tail = &ctl->win_tail[t];
+      tail = &ctl->win_tail[t].v;
       q = a.win + (size_t)t * a.cap;
     } else if (t == K) {
-      tail = &ctl->spill_tail[s.spill_out];
+      tail = &ctl->spill_tail[s.spill_out].v;
       q = a.spill + (size_t)s.spill_out * a.cap;
     } else {
-      tail = &ctl->far_tail[s.far_out];
+      tail = &ctl->far_tail[s.far_out].v;
       q = a.far + (size_t)s.far_out * a.cap;
     }
     unsigned base = 0;
@@ -201,11 +242,11 @@ __device__ void wave_push_global(const Args& a, const Smem& s, Counters& c, bool
     if (mine) {
       const unsigned pos = base + (unsigned)__popcll(mm & lanemask_lt());
       if (pos < a.cap && pos >= base) {
-        q[pos] = make_int2(v, d);
+        st_entry(q, pos, v, d);
         c.push_global++;
         if (t == K + 1) {
           c.far++;
-          atomicMin(&ctl->far_min[s.far_out], b);
+          atomicMin(&ctl->far_min[s.far_out].v, b);
         }
         has = false;
       } else if (t == K + 1) {
@@ -256,22 +297,23 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int v, int d,
   bool repush = false;
   unsigned rb = 0;
   if (v >= 0) {
+    // issued together: the staleness check does not delay the row lookup
     const int cv = a.dist[v];
+    const long long r0 = a.row_ptr[v];
+    const long long r1 = a.row_ptr[v + 1];
+    const unsigned key = bucket_key(a, v, (unsigned)d);
     bool live = d <= cv;
     if (live && from_global) {
-      rb = bucket_of(a, v, (unsigned)d);
+      rb = bucket_of_key(a, key);
       if (rb > s.cur) {
         repush = true;  // a far-list entry that belongs to a later bucket
         live = false;
       }
     }
-    if (live && a.target >= 0) {
-      const unsigned key = a.h ? (unsigned)d + (unsigned)a.h[v] : (unsigned)d;
-      if (key >= (unsigned)s.tbound) live = false;  // cannot improve the target
-    }
+    if (live && a.target >= 0 && key >= (unsigned)s.tbound) live = false;  // cannot improve the target
     if (live) {
-      start = a.row_ptr[v];
-      deg = (int)(a.row_ptr[v + 1] - start);
+      start = r0;
+      deg = (int)(r1 - r0);
     }
   }
   {
@@ -310,17 +352,16 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int v, int d,
         set_status(a.ctl, OG_ERR_OVERFLOW);
       } else {
         bool go = (int)nd < a.dist[u];
-        unsigned key = nd;
-        if (go && a.target >= 0) {
-          if (a.h) key = nd + (unsigned)a.h[u];
-          go = key < (unsigned)tb;
-        }
         if (go) {
-          const int old = atomicMin(&a.dist[u], (int)nd);
-          if ((int)nd < old) {
-            c.improve++;
-            has = true;
-            b = a.shift >= 0 ? ((a.h ? key : nd) >> a.shift) : ((a.h ? key : nd) / a.delta);
+          const unsigned key = bucket_key(a, u, nd);
+          if (a.target >= 0 && key >= (unsigned)tb) go = false;  // cannot improve the target
+          if (go) {
+            const int old = atomicMin(&a.dist[u], (int)nd);
+            if ((int)nd < old) {
+              c.improve++;
+              has = true;
+              b = bucket_of_key(a, key);
+            }
           }
         }
       }
@@ -335,7 +376,7 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int v, int d,
 __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
   const unsigned h = s.lq_head, cnt = s.lq_tail - s.lq_head;
-  if (tid == 0) s.gbase = atomicAdd(&a.ctl->spill_tail[s.spill_out], cnt);
+  if (tid == 0) s.gbase = atomicAdd(&a.ctl->spill_tail[s.spill_out].v, cnt);
   __syncthreads();
   const unsigned gb = s.gbase;
   int2* q = a.spill + (size_t)s.spill_out * a.cap;
@@ -347,7 +388,7 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
       e = s.lq[(h + i) & (kLq - 1)];
       const unsigned pos = gb + i;
       if (pos < a.cap && pos >= gb) {
-        q[pos] = e;
+        st_entry(q, pos, e.x, e.y);
         c.push_global++;
       } else {
         spill_far = true;
@@ -360,9 +401,15 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
 }
 
 // One round: the round input list, then (fused) the local current bucket.
+// A round input that fits in one batch per workgroup is split statically
+// (workgroup b takes the b-th slice, no atomics); a larger one is handed
+// out in kBlock chunks through an atomic cursor.
 __device__ void run_round(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
   const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const unsigned count = s.in_count;
+  const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
+  const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
   if (tid == 0) {
     s.lq_head = s.lq_tail = 0;
     s.exhausted = 0;
@@ -379,11 +426,17 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
         s.mode = 1;
         s.nb = (int)(lsize < (unsigned)kBlock ? lsize : (unsigned)kBlock);
       } else if (!s.exhausted) {
-        const unsigned base = atomicAdd(&a.ctl->in_head, s.chunk);
-        if (base < s.in_count) {
+        unsigned base;
+        if (fixed) {
+          base = (unsigned)blockIdx.x * per;
+          s.exhausted = 1;
+        } else {
+          base = atomicAdd(&a.ctl->in_head.v, (unsigned)kBlock);
+        }
+        if (base < count) {
           s.mode = 2;
-          const unsigned left = s.in_count - base;
-          s.nb = (int)(left < s.chunk ? left : s.chunk);
+          const unsigned left = count - base;
+          s.nb = (int)(left < per ? left : per);
           s.gbase = base;
         } else {
           s.exhausted = 1;
@@ -401,7 +454,7 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
     const int nb = s.nb;
     int v = -1, d = 0;
     if (tid < nb) {
-      const int2 e = mode == 1 ? s.lq[(s.lq_head + tid) & (kLq - 1)] : in[s.gbase + tid];
+      const int2 e = mode == 1 ? s.lq[(s.lq_head + tid) & (kLq - 1)] : ld_entry(in, (size_t)s.gbase + tid);
       v = e.x;
       d = e.y;
     }
@@ -425,25 +478,25 @@ __device__ void decide(const Args& a) {
   Ctl* c = a.ctl;
   const int lane = (int)lane_id();
   const int K = a.K;
-  auto ld = [](const unsigned* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-  const unsigned cur = c->cur;
-  const int in_kind = c->in_kind, in_index = c->in_index;
-  const unsigned round = c->round + 1;
-  int status = __hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int far_in = in_kind == kInFar ? 1 - in_index : c->far_in;
-  const int so = c->spill_out;
-  const unsigned spill_raw = ld(&c->spill_tail[so]);
-  const unsigned far_raw = ld(&c->far_tail[far_in]);
-  const unsigned fmin = far_raw ? ld(&c->far_min[far_in]) : kNoBucket;
+  const unsigned cur = ld_dev(&c->c.cur);
+  const int in_kind = (int)ld_dev(&c->c.in_kind), in_index = (int)ld_dev(&c->c.in_index);
+  const unsigned round = ld_dev(&c->c.round) + 1;
+  const unsigned win_hi = ld_dev(&c->c.win_hi);
+  int status = (int)ld_dev(&c->status.v);
+  const int far_in = in_kind == kInFar ? 1 - in_index : (int)ld_dev(&c->c.far_in);
+  const int so = (int)ld_dev(&c->c.spill_out);
+  const unsigned spill_raw = ld_dev(&c->spill_tail[so].v);
+  const unsigned far_raw = ld_dev(&c->far_tail[far_in].v);
+  const unsigned fmin = far_raw ? ld_dev(&c->far_min[far_in].v) : kNoBucket;
   // window occupancy, lane j looks at bucket cur + j
   unsigned wraw = 0;
   bool nonempty = false;
   if (lane < K) {
     const unsigned slot = (cur + (unsigned)lane) & (unsigned)(K - 1);
     const bool consumed = in_kind == kInWin && (int)slot == in_index;
-    wraw = consumed ? 0u : ld(&c->win_tail[slot]);
+    wraw = consumed ? 0u : ld_dev(&c->win_tail[slot].v);
     const unsigned bk = cur + (unsigned)lane;
-    nonempty = wraw > 0 && bk >= cur && bk < c->win_hi;
+    nonempty = wraw > 0 && bk >= cur && bk < win_hi;
   }
   unsigned long long need_w = wraw;
   for (int o = 32; o >= 1; o >>= 1) {
@@ -454,28 +507,28 @@ __device__ void decide(const Args& a) {
   const unsigned long long ne = __ballot(nonempty) & ~1ull;  // buckets after cur
   if (lane != 0) return;
   // the consumed input list is empty again
-  if (in_kind == kInWin) c->win_tail[in_index] = 0;
-  else if (in_kind == kInSpill) c->spill_tail[in_index] = 0;
+  if (in_kind == kInWin) st_dev(&c->win_tail[in_index].v, 0);
+  else if (in_kind == kInSpill) st_dev(&c->spill_tail[in_index].v, 0);
   else {
-    c->far_tail[in_index] = 0;
-    c->far_min[in_index] = kNoBucket;
+    st_dev(&c->far_tail[in_index].v, 0);
+    st_dev(&c->far_min[in_index].v, kNoBucket);
   }
+  st_dev(&c->in_head.v, 0);
 
-  unsigned long long need = c->need;
+  unsigned long long need = __hip_atomic_load(&c->need.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (need_w > need) need = need_w;
   if (spill_raw > need) need = spill_raw;
   if (far_raw > need) need = far_raw;
-  c->need = need;
+  __hip_atomic_store(&c->need.v, need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
   auto clampcap = [&](unsigned x) { return x < a.cap ? x : a.cap; };
-  int done = 0;
-  unsigned ncur = cur, count = 0, buckets = c->buckets;
+  unsigned done = 0;
+  unsigned ncur = cur, count = 0, buckets = ld_dev(&c->c.buckets), nwin_hi = win_hi;
   int nkind = kInWin, nindex = 0, nspill_out = so;
   if (status != 0) {
     done = 1;
   } else if (a.max_rounds && round >= a.max_rounds) {
-    status = OG_ERR_ROUND_LIMIT;
-    c->status = status;
+    set_status(c, OG_ERR_ROUND_LIMIT);
     done = 1;
   } else if (far_raw && fmin <= cur) {
     nkind = kInFar;
@@ -510,39 +563,79 @@ __device__ void decide(const Args& a) {
         } else {
           nkind = kInWin;
           nindex = (int)(next & (unsigned)(K - 1));
-          count = clampcap(ld(&c->win_tail[nindex]));
+          count = clampcap(ld_dev(&c->win_tail[nindex].v));
         }
-        c->win_hi = sat_add(next, (unsigned)K);
+        nwin_hi = sat_add(next, (unsigned)K);
       }
     }
   }
-  unsigned chunk = (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg;
-  if (chunk < 1) chunk = 1;
-  if (chunk > (unsigned)kBlock) chunk = kBlock;
-  c->cur = ncur;
-  c->in_kind = nkind;
-  c->in_index = nindex;
-  c->in_count = count;
-  c->in_head = 0;
-  c->chunk = chunk;
-  c->spill_out = nspill_out;
-  c->far_in = far_in;
-  c->round = round;
-  c->buckets = buckets;
-  c->done = done;
+  st_dev(&c->c.cur, ncur);
+  st_dev(&c->c.in_kind, (unsigned)nkind);
+  st_dev(&c->c.in_index, (unsigned)nindex);
+  st_dev(&c->c.in_count, count);
+  st_dev(&c->c.spill_out, (unsigned)nspill_out);
+  st_dev(&c->c.far_in, (unsigned)far_in);
+  st_dev(&c->c.win_hi, nwin_hi);
+  st_dev(&c->c.buckets, buckets);
+  st_dev(&c->c.done, done);
+  st_dev(&c->c.round, round);
 }
 
 __device__ void load_control(const Args& a, Smem& s) {
   Ctl* c = a.ctl;
-  s.cur = c->cur;
-  s.in_kind = c->in_kind;
-  s.in_index = c->in_index;
-  s.in_count = c->in_count;
-  s.chunk = c->chunk;
-  s.win_hi = c->win_hi;
-  s.spill_out = c->spill_out;
-  s.far_out = s.in_kind == kInFar ? 1 - c->far_in : c->far_in;
-  s.done = c->done || c->status != 0;
+  s.cur = ld_dev(&c->c.cur);
+  s.in_kind = (int)ld_dev(&c->c.in_kind);
+  s.in_index = (int)ld_dev(&c->c.in_index);
+  s.in_count = ld_dev(&c->c.in_count);
+  s.win_hi = ld_dev(&c->c.win_hi);
+  s.spill_out = (int)ld_dev(&c->c.spill_out);
+  s.round = ld_dev(&c->c.round);
+  const int far_in = (int)ld_dev(&c->c.far_in);
+  s.far_out = s.in_kind == kInFar ? 1 - far_in : far_in;
+  s.done = ld_dev(&c->c.done) || ld_dev(&c->status.v) != 0;
+}
+
+// End-of-round synchronisation across the grid.  Every wavefront waits for
+// its own stores and atomics to complete; thread 0 of each workgroup then
+// arrives on its group's counter (kGroup workgroups per counter, each on its
+// own cache line), the last of a group arrives on the root counter, and the
+// last workgroup overall runs the bucket decision with wave 0 and publishes
+// the next round number on kFlags release flags.  With wait_others (the
+// persistent engine) every other workgroup spins on one of those flags;
+// the host-driven engine ends the kernel instead.
+__device__ void round_barrier(const Args& a, Smem& s, bool wait_others) {
+  Ctl* ctl = a.ctl;
+  wait_vm();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int grp = (int)blockIdx.x / kGroup;
+    const int ngrp = (a.nwg + kGroup - 1) / kGroup;
+    const int gsize = grp == ngrp - 1 ? a.nwg - grp * kGroup : kGroup;
+    bool last = false;
+    const unsigned p = atomicAdd(&ctl->bar_grp[grp].v, 1u);
+    if (p == (unsigned)gsize - 1) {
+      (void)atomicExch(&ctl->bar_grp[grp].v, 0u);
+      const unsigned q = atomicAdd(&ctl->bar_root.v, 1u);
+      if (q == (unsigned)ngrp - 1) {
+        (void)atomicExch(&ctl->bar_root.v, 0u);
+        last = true;
+      }
+    }
+    s.last = last;
+  }
+  __syncthreads();
+  if (s.last) {
+    if (threadIdx.x < kWave) {
+      decide(a);
+      wait_vm();
+      st_dev(&ctl->flag[threadIdx.x].v, s.round + 1);
+    }
+  } else if (wait_others && threadIdx.x == 0) {
+    const unsigned want = s.round + 1;
+    const unsigned* f = &ctl->flag[blockIdx.x % kFlags].v;
+    while (ld_dev(f) < want) __builtin_amdgcn_s_sleep(2);
+  }
+  __syncthreads();
 }
 
 __device__ void flush_counters(const Args& a, const Counters& c) {
@@ -552,11 +645,9 @@ __device__ void flush_counters(const Args& a, const Counters& c) {
     for (int o = 32; o >= 1; o >>= 1) v[i] += __shfl_xor(v[i], o);
   if (lane_id() == 0) {
     Ctl* ctl = a.ctl;
-    if (v[0]) atomicAdd(&ctl->st_relax, v[0]);
-    if (v[1]) atomicAdd(&ctl->st_improve, v[1]);
-    if (v[2]) atomicAdd(&ctl->st_push_local, v[2]);
-    if (v[3]) atomicAdd(&ctl->st_push_global, v[3]);
-    if (v[4]) atomicAdd(&ctl->st_far, v[4]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if (v[i]) atomicAdd(&ctl->st[kStRelax + i].v, v[i]);
   }
 }
 
@@ -566,70 +657,34 @@ __global__ __launch_bounds__(kBlock) void k_init(Args a, int src) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride)
     a.dist[v] = v == src ? 0 : kInf;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Ctl* c = a.ctl;
-    unsigned* words = reinterpret_cast<unsigned*>(c);
-    for (size_t i = 0; i < sizeof(Ctl) / sizeof(unsigned); ++i) words[i] = 0;
-    const unsigned b0 = bucket_of(a, src, 0u);
-    const int slot = (int)(b0 & (unsigned)(a.K - 1));
-    c->cur = b0;
-    c->in_kind = kInWin;
-    c->in_index = slot;
-    c->in_count = 1;
-    c->chunk = 1;
-    c->win_tail[slot] = 1;
-    c->win_hi = sat_add(b0, (unsigned)a.K);
-    c->far_min[0] = c->far_min[1] = kNoBucket;
-    c->buckets = 1;
-    c->need = 1;
-    a.win[(size_t)slot * a.cap] = make_int2(src, 0);
-  }
+  // zero the control block (grid-stride over its words)
+  unsigned* words = reinterpret_cast<unsigned*>(a.ctl);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (long long)(sizeof(Ctl) / 4); i += stride)
+    words[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_ctl(Args a, int src) {
+  if (threadIdx.x != 0) return;
+  Ctl* c = a.ctl;
+  const unsigned b0 = bucket_of_key(a, bucket_key(a, src, 0u));
+  const int slot = (int)(b0 & (unsigned)(a.K - 1));
+  c->c.cur = b0;
+  c->c.in_kind = kInWin;
+  c->c.in_index = slot;
+  c->c.in_count = 1;
+  c->c.win_hi = sat_add(b0, (unsigned)a.K);
+  c->c.buckets = 1;
+  c->win_tail[slot].v = 1;
+  c->far_min[0].v = c->far_min[1].v = kNoBucket;
+  c->need.v = 1;
+  st_entry(a.win, (size_t)slot * a.cap, src, 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_validate(const int* w, long long m, Ctl* ctl) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   bool bad = false;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) bad |= w[e] < 0;
-  if (__ballot(bad) && lane_id() == 0) atomicExch(&ctl->status, OG_ERR_NEGATIVE_WEIGHT);
-}
-
-// End-of-round synchronisation across the whole grid.  Every wavefront
-// releases its global writes at device (agent) scope, thread 0 of each
-// workgroup arrives on a device-wide counter, and the last workgroup to
-// arrive runs the bucket decision with wave 0.  With wait_others (the
-// persistent engine) every other workgroup then spins on the barrier
-// generation until the decision is published and acquires it; the
-// host-driven engine instead ends the kernel.  Returns true if this
-// workgroup ran the decision.
-__device__ bool round_barrier(const Args& a, Smem& s, bool wait_others) {
-  Ctl* ctl = a.ctl;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    s.gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned prev =
-        __hip_atomic_fetch_add(&ctl->bar_arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s.last = prev == (unsigned)a.nwg - 1;
-  }
-  __syncthreads();
-  const bool last = s.last;
-  if (last) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (threadIdx.x < kWave) decide(a);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __hip_atomic_store(&ctl->bar_arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->bar_gen, s.gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else if (wait_others && threadIdx.x == 0) {
-    const unsigned gen = s.gen;
-    while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
-      __builtin_amdgcn_s_sleep(1);
-  }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return last;
+  if (__ballot(bad) && lane_id() == 0) atomicExch(reinterpret_cast<int*>(&ctl->status.v), OG_ERR_NEGATIVE_WEIGHT);
 }
 
 // Persistent engine: one cooperative launch; rounds separated by a
@@ -712,8 +767,8 @@ __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
     re += __shfl_xor(re, o);
   }
   if (lane == 0) {
-    if (rv) atomicAdd(&a.ctl->st_reached_v, rv);
-    if (re) atomicAdd(&a.ctl->st_reached_e, re);
+    if (rv) atomicAdd(&a.ctl->st[kStReachedV].v, rv);
+    if (re) atomicAdd(&a.ctl->st[kStReachedE].v, re);
   }
 }
 
@@ -817,18 +872,18 @@ bool graph_ok(const og_graph* g) {
 
 void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   if (!st) return;
-  st->status = h.status;
+  st->status = (og_status)h.status.v;
   st->workgroups = nwg;
-  st->rounds = h.round;
-  st->buckets = h.buckets;
-  st->relaxations = (int64_t)h.st_relax;
-  st->improvements = (int64_t)h.st_improve;
-  st->pushes_local = (int64_t)h.st_push_local;
-  st->pushes_global = (int64_t)h.st_push_global;
-  st->far_pushes = (int64_t)h.st_far;
-  st->reached_vertices = (int64_t)h.st_reached_v;
-  st->reached_edges = (int64_t)h.st_reached_e;
-  st->queue_needed = (int64_t)h.need;
+  st->rounds = h.c.round;
+  st->buckets = h.c.buckets;
+  st->relaxations = (int64_t)h.st[kStRelax].v;
+  st->improvements = (int64_t)h.st[kStImprove].v;
+  st->pushes_local = (int64_t)h.st[kStPushLocal].v;
+  st->pushes_global = (int64_t)h.st[kStPushGlobal].v;
+  st->far_pushes = (int64_t)h.st[kStFar].v;
+  st->reached_vertices = (int64_t)h.st[kStReachedV].v;
+  st->reached_edges = (int64_t)h.st[kStReachedE].v;
+  st->queue_needed = (int64_t)h.need.v;
 }
 
 og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, const og_schedule* sched,
@@ -859,6 +914,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   int maxwg = di.cus * (di.occ_persistent > 0 ? di.occ_persistent : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
   if (persistent && nwg > maxwg) nwg = maxwg;
+  if (nwg > kMaxWg) nwg = kMaxWg;
   if (nwg < 1) nwg = 1;
 
   const long long cap = queue_cap(g, &r);
@@ -893,6 +949,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   if (timing) hipEventRecord(t_timers.ev[0], stream);
   const int fill_grid = di.cus * 8;
   hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, src);
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a, src);
   if (r.flags & OG_FLAG_VALIDATE)
     hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
@@ -913,11 +970,12 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
     while (!done && launched < cap_launches) {
       for (int i = 0; i < group; ++i) hipLaunchKernelGGL(k_round, dim3(nwg), dim3(kBlock), 0, stream, a);
       launched += group;
-      int hd[2];
-      if (hipMemcpyAsync(hd, &a.ctl->done, sizeof(int) * 2, hipMemcpyDeviceToHost, stream) != hipSuccess)
+      unsigned hd[64];  // the Control line and the status line
+      if (hipMemcpyAsync(hd, a.ctl, sizeof(hd), hipMemcpyDeviceToHost, stream) != hipSuccess)
         return fail(OG_ERR_HIP);
       if (hipStreamSynchronize(stream) != hipSuccess) return fail(OG_ERR_HIP);
-      done = hd[0] || hd[1];
+      const Ctl* hv = reinterpret_cast<const Ctl*>(hd);
+      done = hv->c.done || hv->status.v;
     }
   }
   if (timing) hipEventRecord(t_timers.ev[2], stream);
@@ -934,7 +992,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
     if (stats) stats->workgroups = nwg;
     return OG_OK;
   }
-  Ctl hc;
+  static thread_local Ctl hc;
   if (hipMemcpyAsync(&hc, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return fail(OG_ERR_HIP);
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(OG_ERR_HIP);
@@ -945,7 +1003,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
     if (hipEventElapsedTime(&ms, t_timers.ev[1], t_timers.ev[2]) == hipSuccess) stats->engine_ms = ms;
     if (hipEventElapsedTime(&ms, t_timers.ev[2], t_timers.ev[3]) == hipSuccess) stats->pred_ms = ms;
   }
-  return hc.status;
+  return (og_status)hc.status.v;
 }
 
 }  // namespace og
@@ -1014,13 +1072,13 @@ og_status og_astar(const og_graph* g, int32_t src, int32_t dst, const int32_t* h
 
 og_status og_read_stats(const void* ws, og_stats* stats, void* stream) {
   if (!ws || !stats) return OG_ERR_INVALID_ARG;
-  og::Ctl hc;
+  static thread_local og::Ctl hc;
   hipStream_t st = (hipStream_t)stream;
   if (hipMemcpyAsync(&hc, ws, sizeof(og::Ctl), hipMemcpyDeviceToHost, st) != hipSuccess) return OG_ERR_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) return OG_ERR_HIP;
   const int wg = stats->workgroups;
   og::fill_stats(hc, stats, wg);
-  return hc.status;
+  return (og_status)hc.status.v;
 }
 
 }  // extern "C"

@@ -68,9 +68,9 @@ def test_workspace_bytes():
     g = _fake_graph(1000, 4000)
     s = og.Schedule(delta=4).to_c()
     b = lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s))
-    assert b % 256 == 0 and b >= 4096 + (16 + 4) * 1024 * 8
+    assert b % 256 == 0 and b >= 65536 + (16 + 4) * 1024 * 8
     s2 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000).to_c()
-    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 4096 + 12 * 5000 * 8
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 65536 + 12 * 5000 * 8
     bad = og.Schedule(delta=0).to_c()
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
     g0 = _lib.OgGraph(0, 0, 0x1000, None, None)
