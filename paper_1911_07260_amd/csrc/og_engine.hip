@@ -946,14 +946,14 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   a.far = a.spill + 2 * (size_t)cap;
 
   const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
-  if (timing) hipEventRecord(t_timers.ev[0], stream);
+  if (timing) (void)hipEventRecord(t_timers.ev[0], stream);
   const int fill_grid = di.cus * 8;
   hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, src);
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a, src);
   if (r.flags & OG_FLAG_VALIDATE)
     hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
-  if (timing) hipEventRecord(t_timers.ev[1], stream);
+  if (timing) (void)hipEventRecord(t_timers.ev[1], stream);
 
   if (persistent) {
     void* kargs[] = {&a};
@@ -978,7 +978,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
       done = hv->c.done || hv->status.v;
     }
   }
-  if (timing) hipEventRecord(t_timers.ev[2], stream);
+  if (timing) (void)hipEventRecord(t_timers.ev[2], stream);
   if (pred) {
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, g->n, kInf);
     hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
@@ -986,7 +986,7 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   } else if (stats) {
     hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
   }
-  if (timing) hipEventRecord(t_timers.ev[3], stream);
+  if (timing) (void)hipEventRecord(t_timers.ev[3], stream);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
   if (r.flags & OG_FLAG_ASYNC) {
     if (stats) stats->workgroups = nwg;
