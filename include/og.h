@@ -121,6 +121,11 @@ typedef struct og_stats {
   double init_ms;           /* OG_FLAG_TIMING: initialisation kernel          */
   double engine_ms;         /* OG_FLAG_TIMING: bucket engine (all rounds)     */
   double pred_ms;           /* OG_FLAG_TIMING: predecessor / counting pass    */
+  int64_t batches;          /* batches of up to 256 entries processed, summed
+                               over workgroups                                */
+  int64_t chain;            /* sum over rounds of the most batches any one
+                               workgroup processed in that round (the engine's
+                               critical path in batch steps)                  */
 } og_stats;
 
 /* Library version, (major << 16) | minor. */
@@ -166,6 +171,39 @@ og_status og_ppsp(const og_graph* g, int32_t src, int32_t dst, const og_schedule
 og_status og_astar(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, const og_schedule* s,
                    int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats,
                    void* stream);
+
+/* ---- Several queries in one launch ------------------------------------
+ * Query q works on its own copy of the graph (virtual vertex q * n + v);
+ * all queries share one bucket sequence, so a single persistent launch
+ * serves the whole batch.  Requires nq * n < 2^31 and nq <= 1024.  srcs and
+ * dsts are HOST arrays of nq base vertex ids; dist and pred are DEVICE arrays
+ * of nq * n entries, query q's results at [q * n, (q + 1) * n) (pred holds
+ * base vertex ids).  The workspace must hold og_workspace_bytes_batch(). */
+size_t og_workspace_bytes_batch(const og_graph* g, const og_schedule* s, int32_t nq);
+
+/* nq independent single-source queries (og_sssp semantics per query). */
+og_status og_sssp_batch(const og_graph* g, const int32_t* srcs, int32_t nq, const og_schedule* s, int32_t* dist,
+                        int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream);
+
+/* nq point-to-point queries (og_ppsp semantics per query): the launch stops
+ * before a bucket i with i*Delta >= dist of every query's target. */
+og_status og_ppsp_batch(const og_graph* g, const int32_t* srcs, const int32_t* dsts, int32_t nq,
+                        const og_schedule* s, int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes,
+                        og_stats* stats, void* stream);
+
+/* nq A* queries (og_astar semantics per query); h is a DEVICE array of
+ * nq * n estimates, query q's at [q * n, (q + 1) * n). */
+og_status og_astar_batch(const og_graph* g, const int32_t* srcs, const int32_t* dsts, int32_t nq, const int32_t* h,
+                         const og_schedule* s, int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes,
+                         og_stats* stats, void* stream);
+
+/* Multi-source shortest paths: dist[v] = min over the nsrc sources (HOST
+ * array) of the shortest distance to v; pred[src] = src for every source.
+ * Many disjoint graphs stored as one block-diagonal CSR, one source each,
+ * are solved in one launch this way.  Workspace: og_workspace_bytes_multi(). */
+size_t og_workspace_bytes_multi(const og_graph* g, const og_schedule* s, int32_t nsrc);
+og_status og_sssp_multi(const og_graph* g, const int32_t* srcs, int32_t nsrc, const og_schedule* s, int32_t* dist,
+                        int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream);
 
 /* Reads the status and counters of the last call made with workspace ws
  * (device) into *stats (host); used after an OG_FLAG_ASYNC call once the

@@ -28,8 +28,8 @@ from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_HOST_ROUN
 INF = 2**31 - 1
 
 __all__ = [
-    "DeviceGraph", "Schedule", "Workspace", "sssp", "wbfs", "ppsp", "astar", "workspace_bytes",
-    "status_string", "version", "INF", "OgError",
+    "DeviceGraph", "Schedule", "Workspace", "sssp", "wbfs", "ppsp", "astar", "sssp_batch", "ppsp_batch",
+    "astar_batch", "sssp_multi", "workspace_bytes", "status_string", "version", "INF", "OgError",
 ]
 
 
@@ -90,10 +90,16 @@ def status_string(status: int) -> str:
     return _lib.load().og_status_string(int(status)).decode()
 
 
-def workspace_bytes(graph: DeviceGraph, schedule: Schedule) -> int:
+def workspace_bytes(graph: DeviceGraph, schedule: Schedule, batch: int = 0, multi: int = 0) -> int:
+    """og_workspace_bytes (single query), ..._batch (batch = nq queries) or
+    ..._multi (multi = number of sources)."""
     lib = _lib.load()
     g = graph.to_c()
     s = schedule.to_c()
+    if batch:
+        return int(lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(s), int(batch)))
+    if multi:
+        return int(lib.og_workspace_bytes_multi(ctypes.byref(g), ctypes.byref(s), int(multi)))
     return int(lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s)))
 
 
@@ -114,8 +120,8 @@ class Workspace:
 _default_ws: dict = {}
 
 
-def _workspace(graph: DeviceGraph, schedule: Schedule, ws: Workspace | None):
-    nbytes = workspace_bytes(graph, schedule)
+def _workspace(graph: DeviceGraph, schedule: Schedule, ws: Workspace | None, batch: int = 0, multi: int = 0):
+    nbytes = workspace_bytes(graph, schedule, batch=batch, multi=multi)
     if nbytes == 0:
         raise OgError(OG_ERR_INVALID_ARG, "og_workspace_bytes", _lib.load())
     if ws is None:
@@ -125,15 +131,17 @@ def _workspace(graph: DeviceGraph, schedule: Schedule, ws: Workspace | None):
 
 
 def _call(fn_name, graph, args_mid, schedule, want_pred, ws, stream, out_dist=None, out_pred=None,
-          check=True):
+          check=True, nq=1, batch=0, multi=0):
     lib = _lib.load()
     schedule = schedule or Schedule()
-    n = graph.n
+    n = graph.n * nq
     dev = graph.device
-    dist = out_dist if out_dist is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    shape = (nq, graph.n) if batch else (graph.n,)
+    dist = out_dist if out_dist is not None else torch.empty(shape, dtype=torch.int32, device=dev)
     pred = out_pred if out_pred is not None else (
-        torch.empty(n, dtype=torch.int32, device=dev) if want_pred else None)
-    buf, nbytes = _workspace(graph, schedule, ws)
+        torch.empty(shape, dtype=torch.int32, device=dev) if want_pred else None)
+    assert dist.numel() == n and dist.dtype == torch.int32 and dist.is_contiguous()
+    buf, nbytes = _workspace(graph, schedule, ws, batch=batch, multi=multi)
     g = graph.to_c()
     s = schedule.to_c()
     st = OgStats()
@@ -176,3 +184,45 @@ def astar(graph: DeviceGraph, src: int, dst: int, h: torch.Tensor, schedule: Sch
     assert h.dtype == torch.int32 and h.is_contiguous() and h.numel() == graph.n
     return _call("og_astar", graph, [int(src), int(dst), ctypes.c_void_p(h.data_ptr())], schedule, pred,
                  ws, stream, **kw)
+
+
+def _host_ids(a) -> "np.ndarray":
+    import numpy as np
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+
+
+def sssp_batch(graph: DeviceGraph, srcs, schedule: Schedule | None = None, pred: bool = True,
+               ws: Workspace | None = None, stream=None, **kw):
+    """nq single-source queries in one launch (og_sssp_batch); dist and pred
+    are [nq, n]."""
+    s_ = _host_ids(srcs)
+    return _call("og_sssp_batch", graph, [ctypes.c_void_p(s_.ctypes.data), len(s_)], schedule, pred, ws, stream,
+                 nq=len(s_), batch=len(s_), **kw)
+
+
+def ppsp_batch(graph: DeviceGraph, srcs, dsts, schedule: Schedule | None = None, pred: bool = True,
+               ws: Workspace | None = None, stream=None, **kw):
+    """nq point-to-point queries in one launch (og_ppsp_batch)."""
+    s_, t_ = _host_ids(srcs), _host_ids(dsts)
+    assert len(s_) == len(t_)
+    return _call("og_ppsp_batch", graph, [ctypes.c_void_p(s_.ctypes.data), ctypes.c_void_p(t_.ctypes.data), len(s_)],
+                 schedule, pred, ws, stream, nq=len(s_), batch=len(s_), **kw)
+
+
+def astar_batch(graph: DeviceGraph, srcs, dsts, h: torch.Tensor, schedule: Schedule | None = None,
+                pred: bool = True, ws: Workspace | None = None, stream=None, **kw):
+    """nq A* queries in one launch (og_astar_batch); h is [nq, n] int32."""
+    s_, t_ = _host_ids(srcs), _host_ids(dsts)
+    assert len(s_) == len(t_)
+    assert h.dtype == torch.int32 and h.is_contiguous() and h.numel() == graph.n * len(s_)
+    return _call("og_astar_batch", graph, [ctypes.c_void_p(s_.ctypes.data), ctypes.c_void_p(t_.ctypes.data), len(s_),
+                                           ctypes.c_void_p(h.data_ptr())],
+                 schedule, pred, ws, stream, nq=len(s_), batch=len(s_), **kw)
+
+
+def sssp_multi(graph: DeviceGraph, srcs, schedule: Schedule | None = None, pred: bool = True,
+               ws: Workspace | None = None, stream=None, **kw):
+    """Multi-source shortest paths (og_sssp_multi): dist[v] = min over srcs."""
+    s_ = _host_ids(srcs)
+    return _call("og_sssp_multi", graph, [ctypes.c_void_p(s_.ctypes.data), len(s_)], schedule, pred, ws, stream,
+                 multi=len(s_), **kw)

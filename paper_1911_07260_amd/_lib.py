@@ -72,6 +72,8 @@ class OgStats(ctypes.Structure):
         ("init_ms", ctypes.c_double),
         ("engine_ms", ctypes.c_double),
         ("pred_ms", ctypes.c_double),
+        ("batches", ctypes.c_int64),
+        ("chain", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -119,6 +121,18 @@ def load():
     lib.og_ppsp.argtypes = [P(OgGraph), i32, i32] + common
     lib.og_astar.restype = i32
     lib.og_astar.argtypes = [P(OgGraph), i32, i32, vp] + common
+    lib.og_workspace_bytes_batch.restype = ctypes.c_size_t
+    lib.og_workspace_bytes_batch.argtypes = [P(OgGraph), P(OgSchedule), i32]
+    lib.og_workspace_bytes_multi.restype = ctypes.c_size_t
+    lib.og_workspace_bytes_multi.argtypes = [P(OgGraph), P(OgSchedule), i32]
+    lib.og_sssp_batch.restype = i32
+    lib.og_sssp_batch.argtypes = [P(OgGraph), vp, i32] + common
+    lib.og_ppsp_batch.restype = i32
+    lib.og_ppsp_batch.argtypes = [P(OgGraph), vp, vp, i32] + common
+    lib.og_astar_batch.restype = i32
+    lib.og_astar_batch.argtypes = [P(OgGraph), vp, vp, i32, vp] + common
+    lib.og_sssp_multi.restype = i32
+    lib.og_sssp_multi.argtypes = [P(OgGraph), vp, i32] + common
     lib.og_read_stats.restype = i32
     lib.og_read_stats.argtypes = [vp, P(OgStats), vp]
     _lib = lib

@@ -6,11 +6,11 @@
 //     current bucket; later buckets go to device-wide bucket queues (a
 //     window of K materialised buckets plus an overflow "far" queue, the
 //     same idea as keeping only a few buckets materialised in section 5.1).
-//   - A round processes the round's input list (the current bucket) with
-//     dynamic chunking across workgroups; every relaxation is a 32-bit
-//     atomic minimum on dist (section 3.2, Dist[e.dst] = min(...)), and an
-//     improved vertex is inserted at once into the bucket of its new
-//     priority floor(d / Delta) (eager update, section 2 coarsening).
+//   - A round processes the round's input list (the current bucket) split
+//     across workgroups; every relaxation is a 32-bit atomic minimum on dist
+//     (section 3, Dist[e.dst] = min(...)), and an improved vertex is inserted
+//     at once into the bucket of its new priority floor(d / Delta) (eager
+//     update, section 2 coarsening).
 //   - Bucket fusion (section 3.3): after its share of the round input, a
 //     workgroup keeps draining its LDS current-bucket ring with no global
 //     synchronisation while the ring holds fewer entries than the fusion
@@ -22,6 +22,14 @@
 //   - Stale entries are never removed from queues: entries carry (v, d) and
 //     are skipped when d > dist[v] (insert without delete).
 //
+// Several queries run in one launch over "virtual vertices": query q's copy
+// of base vertex v is q * n + v, with its own slot in dist (and pred) and the
+// base CSR shared by all copies.  A batch of single-source queries on one
+// graph is the disjoint union of q copies with one source each; a
+// multi-source query (one copy, several sources at distance 0) covers many
+// disjoint graphs stored as one block-diagonal CSR.  All queries share the
+// bucket sequence, so they advance together through the same rounds.
+//
 // Correctness does not depend on the cache coherence of plain loads of
 // dist: dist only decreases during a call, a plain load returns some past
 // value (>= the current one), and every decision that matters is taken on
@@ -29,10 +37,12 @@
 // carried in the queue entry.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "og.h"
 
@@ -41,20 +51,23 @@ namespace og {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kLq = 2048;  // LDS ring entries (power of two)
+constexpr int kLq = 1024;  // LDS ring entries (power of two)
 constexpr int kKmax = 64;
 constexpr int kDefaultK = 16;
 constexpr int kDefaultThreshold = 1024;
-constexpr int kGroup = 16;   // workgroups per first-level barrier counter
+constexpr int kGroup = 16;  // workgroups per first-level barrier counter
 constexpr int kMaxWg = 4096;
 constexpr int kMaxGroups = kMaxWg / kGroup;
-constexpr int kFlags = 64;   // release flags, one per 128-byte line
+constexpr int kFlags = 64;  // release flags, one per 128-byte line
+constexpr int kMaxQueries = 1024;
 constexpr size_t kCtlBytes = 65536;
 constexpr unsigned kNoBucket = 0xffffffffu;
 constexpr int kInf = INT_MAX;
 
 enum : int { kInWin = 0, kInSpill = 1, kInFar = 2 };
-enum : int { kStRelax, kStImprove, kStPushLocal, kStPushGlobal, kStFar, kStReachedV, kStReachedE, kStCount };
+enum : int {
+  kStRelax, kStImprove, kStPushLocal, kStPushGlobal, kStFar, kStBatches, kStReachedV, kStReachedE, kStChain, kStCount
+};
 
 // Every counter that many workgroups update sits on its own 128-byte line.
 struct alignas(128) Word {
@@ -90,6 +103,7 @@ struct Ctl {
   Word spill_tail[2];
   Word far_tail[2];
   Word far_min[2];
+  Word round_max_batches;  // most batches one workgroup ran in the current round
   Word64 need;
   Word64 st[kStCount];
 };
@@ -99,10 +113,14 @@ struct Args {
   const long long* row_ptr;
   const int* col;
   const int* w;
-  int* dist;
-  const int* h;  // A* estimate or nullptr
-  int n;
-  int target;  // -1 for SSSP / wBFS
+  int* dist;     // [n] virtual vertices
+  const int* h;  // [n] A* estimate or nullptr
+  int n;         // virtual vertices = reps * nbase
+  int nbase;     // vertices of the base graph
+  int reps;      // copies (queries)
+  const int* srcs;  // [nsrc] virtual source ids (query table)
+  int nsrc;
+  const int* tgts;  // [reps] virtual target ids, or nullptr (no early exit)
   unsigned delta;
   int shift;  // log2(delta) when delta is a power of two, else -1
   int K;      // window buckets (power of two)
@@ -118,21 +136,24 @@ struct Args {
 };
 
 struct Counters {
-  unsigned long long relax = 0, improve = 0, push_local = 0, push_global = 0, far = 0;
+  unsigned long long relax = 0, improve = 0, push_local = 0, push_global = 0, far = 0, batches = 0;
+  unsigned round_batches = 0;
 };
 
 struct Smem {
-  int2 lq[kLq];
-  long long bstart[kBlock];
-  int boff[kBlock];
+  int4 lq[kLq];        // local current bucket: (v, d, base row start, out-degree)
+  int bstart[kBlock];  // batch: base row start, degree offset, distance, vertex,
+  int boff[kBlock];    //        virtual offset of the vertex's copy
   int bd[kBlock];
+  int bv[kBlock];
+  int bvo[kBlock];
+  int tb[kMaxQueries];  // per-query bound: current dist of the target
   int wsum[kWaves];
-  unsigned lq_head, lq_tail;
+  unsigned lq_head, lq_tail, bhead;
   int mode, nb;
   unsigned gbase;
   int exhausted;
   int last;
-  int tbound;
   // snapshot of the control block for this round
   unsigned cur, in_count, win_hi, round;
   int in_kind, in_index, done, spill_out, far_out;
@@ -171,6 +192,10 @@ __device__ __forceinline__ unsigned bucket_key(const Args& a, int v, unsigned d)
 __device__ __forceinline__ unsigned bucket_of_key(const Args& a, unsigned key) {
   return a.shift >= 0 ? (key >> a.shift) : (key / a.delta);
 }
+// query (copy) of a virtual vertex
+__device__ __forceinline__ int query_of(const Args& a, int v) {
+  return a.reps == 1 ? 0 : (int)((unsigned)v / (unsigned)a.nbase);
+}
 
 __device__ __forceinline__ unsigned sat_add(unsigned x, unsigned y) {
   return x > 0xffffffffu - y ? 0xffffffffu : x + y;
@@ -185,7 +210,8 @@ __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
   return base + (size_t)index * a.cap;
 }
 
-// Block-wide exclusive prefix sum of x; *total receives the sum.
+// Block-wide exclusive prefix sum of x; *total receives the sum.  The
+// per-wave totals are reused only after the caller's next barrier.
 __device__ int block_excl_scan(int x, Smem& s, int* total) {
   const int lane = (int)lane_id(), wid = threadIdx.x / kWave;
   int v = x;
@@ -203,7 +229,6 @@ __device__ int block_excl_scan(int x, Smem& s, int* total) {
     pre += i < wid ? t : 0;
     tot += t;
   }
-  __syncthreads();
   *total = tot;
   return pre + v - x;
 }
@@ -260,11 +285,12 @@ __device__ void wave_push_global(const Args& a, const Smem& s, Counters& c, bool
 }
 
 // Routes one improved vertex per lane: the current bucket goes to the LDS
-// ring when fusing (falling back to the spill list when the ring is full),
-// later buckets to their window slot or the far list.
-__device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v, int d, unsigned b) {
+// ring when fusing, together with its CSR row so the next hop needs no row
+// lookup (falling back to the spill list when the ring is full); later
+// buckets go to their window slot or the far list.
+__device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v, int d, unsigned b, int r0,
+                           int deg) {
   const unsigned cur = s.cur;
-  if (has && b < cur) b = cur;  // only an inconsistent A* estimate gets here
   const bool local = has && a.fused && b == cur;
   const unsigned long long m = __ballot(local);
   if (m) {
@@ -275,7 +301,7 @@ __device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v,
     if (local) {
       const unsigned pos = base + (unsigned)__popcll(m & lanemask_lt());
       if (pos - s.lq_head < (unsigned)kLq) {
-        s.lq[pos & (kLq - 1)] = make_int2(v, d);
+        s.lq[pos & (kLq - 1)] = make_int4(v, d, r0, deg);
         c.push_local++;
         has = false;
       }
@@ -286,34 +312,49 @@ __device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v,
   wave_push_global(a, s, c, has, tgt, v, d, b);
 }
 
-// Relaxes the out-edges of one batch of up to kBlock entries (v, d); lane i
-// holds entry i (v < 0: none).  Edges of the batch are spread evenly over the
+// Relaxes the out-edges of one batch of up to kBlock entries; lane i holds
+// entry i (v < 0: none).  Edges of the batch are spread evenly over the
 // workgroup (flat expansion with a binary search over degree offsets), so a
 // high-degree vertex is shared by all lanes.
-__device__ void process_batch(const Args& a, Smem& s, Counters& c, int v, int d, bool from_global) {
+//
+// from_lds: entries come from the local ring and carry their CSR row.  The
+// staleness check (d > dist[v]) is then made per edge, with the dist load
+// issued together with the edge loads, and no pre-load of dist[u] filters
+// the atomic minimum: a locally chased hop costs two dependent global round
+// trips (edge loads, then the atomic together with the next vertex's row).
+// Otherwise (a global list) the row is looked up per entry and a plain load
+// of dist[u] skips atomics that cannot succeed.
+__device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds) {
   const int tid = threadIdx.x;
-  int deg = 0;
-  long long start = 0;
+  const int v = ent.x, d = ent.y;
+  int deg = 0, start = 0, voff = 0;
   bool repush = false;
   unsigned rb = 0;
   if (v >= 0) {
-    // issued together: the staleness check does not delay the row lookup
-    const int cv = a.dist[v];
-    const long long r0 = a.row_ptr[v];
-    const long long r1 = a.row_ptr[v + 1];
-    const unsigned key = bucket_key(a, v, (unsigned)d);
-    bool live = d <= cv;
-    if (live && from_global) {
-      rb = bucket_of_key(a, key);
-      if (rb > s.cur) {
-        repush = true;  // a far-list entry that belongs to a later bucket
-        live = false;
+    const int vb = a.reps == 1 ? v : (int)((unsigned)v % (unsigned)a.nbase);
+    voff = v - vb;
+    if (from_lds) {
+      start = ent.z;
+      deg = ent.w;
+    } else {
+      // issued together: the staleness check does not delay the row lookup
+      const int cv = a.dist[v];
+      const long long r0 = a.row_ptr[vb];
+      const long long r1 = a.row_ptr[vb + 1];
+      const unsigned key = bucket_key(a, v, (unsigned)d);
+      bool live = d <= cv;
+      if (live) {
+        rb = bucket_of_key(a, key);
+        if (rb > s.cur) {
+          repush = true;  // a far-list entry that belongs to a later bucket
+          live = false;
+        }
       }
-    }
-    if (live && a.target >= 0 && key >= (unsigned)s.tbound) live = false;  // cannot improve the target
-    if (live) {
-      start = r0;
-      deg = (int)(r1 - r0);
+      if (live && a.tgts && key >= (unsigned)s.tb[query_of(a, v)]) live = false;  // cannot improve the target
+      if (live) {
+        start = (int)r0;
+        deg = (int)(r1 - r0);
+      }
     }
   }
   {
@@ -326,13 +367,15 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int v, int d,
   s.boff[tid] = off;
   s.bstart[tid] = start;
   s.bd[tid] = d;
+  s.bv[tid] = v;
+  s.bvo[tid] = voff;
   __syncthreads();
   const int nb = s.nb;
-  const int tb = s.tbound;
+  const unsigned cur = s.cur;
   for (int base = 0; base < total; base += kBlock) {
     const int e = base + tid;
     bool has = false;
-    int u = 0;
+    int u = 0, r0 = 0, rdeg = 0;
     unsigned nd = 0, b = 0;
     if (e < total) {
       int lo = 0, hi = nb - 1;
@@ -341,32 +384,42 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int v, int d,
         if (s.boff[mid] <= e) lo = mid;
         else hi = mid - 1;
       }
-      const long long edge = s.bstart[lo] + (long long)(e - s.boff[lo]);
-      u = a.col[edge];
+      const int edge = s.bstart[lo] + (e - s.boff[lo]);
+      const int dsrc = s.bd[lo];
+      const int ub = a.col[edge];
       const int wt = a.w[edge];
+      const int dnow = from_lds ? a.dist[s.bv[lo]] : dsrc;
+      u = ub + s.bvo[lo];
       c.relax++;
-      nd = (unsigned)s.bd[lo] + (unsigned)wt;
+      nd = (unsigned)dsrc + (unsigned)wt;
       if (wt < 0) {
         set_status(a.ctl, OG_ERR_NEGATIVE_WEIGHT);
       } else if (nd >= (unsigned)kInf) {
         set_status(a.ctl, OG_ERR_OVERFLOW);
-      } else {
-        bool go = (int)nd < a.dist[u];
+      } else if (dsrc <= dnow) {
+        const unsigned key = bucket_key(a, u, nd);
+        bool go = !(a.tgts && key >= (unsigned)s.tb[query_of(a, u)]);  // cannot improve the target
+        if (go && !from_lds) go = (int)nd < a.dist[u];
         if (go) {
-          const unsigned key = bucket_key(a, u, nd);
-          if (a.target >= 0 && key >= (unsigned)tb) go = false;  // cannot improve the target
-          if (go) {
-            const int old = atomicMin(&a.dist[u], (int)nd);
-            if ((int)nd < old) {
-              c.improve++;
-              has = true;
-              b = bucket_of_key(a, key);
-            }
+          b = bucket_of_key(a, key);
+          if (b < cur) b = cur;  // only an inconsistent A* estimate gets here
+          long long q0 = 0, q1 = 0;
+          const bool chase = a.fused && b == cur;
+          if (chase) {  // the next hop's row, fetched alongside the atomic
+            q0 = a.row_ptr[ub];
+            q1 = a.row_ptr[ub + 1];
+          }
+          const int old = atomicMin(&a.dist[u], (int)nd);
+          if ((int)nd < old) {
+            c.improve++;
+            has = true;
+            r0 = (int)q0;
+            rdeg = (int)(q1 - q0);
           }
         }
       }
     }
-    route_push(a, s, c, has, u, (int)nd, b);
+    route_push(a, s, c, has, u, (int)nd, b, r0, rdeg);
   }
 }
 
@@ -383,7 +436,7 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
   for (unsigned i0 = 0; i0 < cnt; i0 += kBlock) {
     const unsigned i = i0 + tid;
     bool spill_far = false;
-    int2 e = make_int2(0, 0);
+    int4 e = make_int4(0, 0, 0, 0);
     if (i < cnt) {
       e = s.lq[(h + i) & (kLq - 1)];
       const unsigned pos = gb + i;
@@ -415,6 +468,7 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
     s.exhausted = 0;
   }
   for (;;) {
+    // (ring pushes of the previous batch are complete: end-of-batch barrier)
     __syncthreads();
     if (tid == 0) {
       if (s.lq_tail - s.lq_head > (unsigned)kLq) s.lq_tail = s.lq_head + kLq;  // burned reservations
@@ -425,6 +479,8 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
       } else if (lsize > 0) {
         s.mode = 1;
         s.nb = (int)(lsize < (unsigned)kBlock ? lsize : (unsigned)kBlock);
+        s.bhead = s.lq_head;
+        s.lq_head += (unsigned)s.nb;  // entries are read before any push of this batch
       } else if (!s.exhausted) {
         unsigned base;
         if (fixed) {
@@ -442,7 +498,6 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
           s.exhausted = 1;
         }
       }
-      if (a.target >= 0 && s.mode != 0) s.tbound = a.dist[a.target];
     }
     __syncthreads();
     const int mode = s.mode;
@@ -451,29 +506,34 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
       publish_local(a, s, c);
       continue;
     }
-    const int nb = s.nb;
-    int v = -1, d = 0;
-    if (tid < nb) {
-      const int2 e = mode == 1 ? s.lq[(s.lq_head + tid) & (kLq - 1)] : ld_entry(in, (size_t)s.gbase + tid);
-      v = e.x;
-      d = e.y;
+    if (a.tgts) {
+      for (int q = tid; q < a.reps; q += kBlock) s.tb[q] = a.dist[a.tgts[q]];
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0 && mode == 1) s.lq_head += nb;
-    __syncthreads();
-    process_batch(a, s, c, v, d, mode == 2);
+    int4 ent = make_int4(-1, 0, 0, 0);
+    if (tid < s.nb) {
+      if (mode == 1) {
+        ent = s.lq[(s.bhead + tid) & (kLq - 1)];
+      } else {
+        const int2 e = ld_entry(in, (size_t)s.gbase + tid);
+        ent = make_int4(e.x, e.y, 0, 0);
+      }
+    }
+    process_batch(a, s, c, ent, mode == 1);
+    c.batches++;
+    c.round_batches++;
   }
 }
 
 // Bucket decision, executed by wave 0 of the last workgroup to finish a
 // round, while every other workgroup waits (persistent engine) or has
 // exited (host-driven engine).  Chooses the next round's input:
-//   1. far entries of the current bucket (overflow),
+//   1. far entries of the current bucket (overflow, or the initial sources),
 //   2. the window slot of the current bucket (after such a far round),
 //   3. the spill list: the same bucket needs another round,
 //   4. otherwise the next non-empty bucket (section 3.2: smallest bucket
 //      across workers), or stop (nothing left, or PPSP / A*: that bucket's
-//      lower bound i*Delta already reaches the target's distance).
+//      lower bound i*Delta already reaches every target's distance).
 __device__ void decide(const Args& a) {
   Ctl* c = a.ctl;
   const int lane = (int)lane_id();
@@ -503,6 +563,17 @@ __device__ void decide(const Args& a) {
     unsigned long long y = __shfl_xor(need_w, o);
     need_w = need_w > y ? need_w : y;
   }
+  // largest current distance among the targets (INF while one is unreached)
+  unsigned tmax = 0;
+  if (a.tgts)
+    for (int q = lane; q < a.reps; q += kWave) {
+      const unsigned dt = (unsigned)__hip_atomic_load(&a.dist[a.tgts[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      tmax = dt > tmax ? dt : tmax;
+    }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned y = __shfl_xor(tmax, o);
+    tmax = y > tmax ? y : tmax;
+  }
   const unsigned slot_cur_cnt = __shfl(wraw, 0);
   const unsigned long long ne = __ballot(nonempty) & ~1ull;  // buckets after cur
   if (lane != 0) return;
@@ -514,6 +585,10 @@ __device__ void decide(const Args& a) {
     st_dev(&c->far_min[in_index].v, kNoBucket);
   }
   st_dev(&c->in_head.v, 0);
+  {
+    const unsigned rm = __hip_atomic_exchange(&c->round_max_batches.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicAdd(&c->st[kStChain].v, (unsigned long long)rm);
+  }
 
   unsigned long long need = __hip_atomic_load(&c->need.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (need_w > need) need = need_w;
@@ -548,25 +623,22 @@ __device__ void decide(const Args& a) {
     const unsigned next = wnext < fmin ? wnext : fmin;
     if (next == kNoBucket) {
       done = 1;
+    } else if (a.tgts && tmax != (unsigned)kInf &&
+               (unsigned long long)next * a.delta >= (unsigned long long)tmax) {
+      done = 1;
     } else {
-      if (a.target >= 0) {
-        const int dt = __hip_atomic_load(&a.dist[a.target], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (dt != kInf && (unsigned long long)next * a.delta >= (unsigned long long)dt) done = 1;
+      ncur = next;
+      buckets++;
+      if (fmin == next) {
+        nkind = kInFar;
+        nindex = far_in;
+        count = clampcap(far_raw);
+      } else {
+        nkind = kInWin;
+        nindex = (int)(next & (unsigned)(K - 1));
+        count = clampcap(ld_dev(&c->win_tail[nindex].v));
       }
-      if (!done) {
-        ncur = next;
-        buckets++;
-        if (fmin == next) {
-          nkind = kInFar;
-          nindex = far_in;
-          count = clampcap(far_raw);
-        } else {
-          nkind = kInWin;
-          nindex = (int)(next & (unsigned)(K - 1));
-          count = clampcap(ld_dev(&c->win_tail[nindex].v));
-        }
-        nwin_hi = sat_add(next, (unsigned)K);
-      }
+      nwin_hi = sat_add(next, (unsigned)K);
     }
   }
   st_dev(&c->c.cur, ncur);
@@ -603,8 +675,10 @@ __device__ void load_control(const Args& a, Smem& s) {
 // the next round number on kFlags release flags.  With wait_others (the
 // persistent engine) every other workgroup spins on one of those flags;
 // the host-driven engine ends the kernel instead.
-__device__ void round_barrier(const Args& a, Smem& s, bool wait_others) {
+__device__ void round_barrier(const Args& a, Smem& s, Counters& c, bool wait_others) {
   Ctl* ctl = a.ctl;
+  if (threadIdx.x == 0) atomicMax(&ctl->round_max_batches.v, c.round_batches);
+  c.round_batches = 0;
   wait_vm();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -648,36 +722,65 @@ __device__ void flush_counters(const Args& a, const Counters& c) {
 #pragma unroll
     for (int i = 0; i < 5; ++i)
       if (v[i]) atomicAdd(&ctl->st[kStRelax + i].v, v[i]);
+    if (threadIdx.x == 0 && c.batches) atomicAdd(&ctl->st[kStBatches].v, c.batches);
   }
 }
 
 // ---------------------------------------------------------------- kernels
 
-__global__ __launch_bounds__(kBlock) void k_init(Args a, int src) {
+// Writes up to kTableChunk entries of the query table (sources, then
+// targets) into the workspace; the values travel in the kernel arguments,
+// so the host buffer need not outlive the call.
+constexpr int kTableChunk = 240;
+struct TableChunk {
+  int offset, count;
+  int vals[kTableChunk];
+};
+__global__ void k_put_table(int* table, TableChunk tc) {
+  for (int i = threadIdx.x; i < tc.count; i += blockDim.x) table[tc.offset + i] = tc.vals[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_init(Args a) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride)
-    a.dist[v] = v == src ? 0 : kInf;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) a.dist[v] = kInf;
   // zero the control block (grid-stride over its words)
   unsigned* words = reinterpret_cast<unsigned*>(a.ctl);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (long long)(sizeof(Ctl) / 4); i += stride)
     words[i] = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_init_ctl(Args a, int src) {
-  if (threadIdx.x != 0) return;
+// Sources: dist = 0, one (s, 0) entry each in far list 0, far_min = the
+// smallest source bucket.  The first round is a far round: it processes the
+// sources of the smallest bucket and files the others (A* estimates can put
+// sources of different queries in different buckets).
+__global__ __launch_bounds__(kBlock) void k_init_sources(Args a) {
   Ctl* c = a.ctl;
-  const unsigned b0 = bucket_of_key(a, bucket_key(a, src, 0u));
-  const int slot = (int)(b0 & (unsigned)(a.K - 1));
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.nsrc; i += gridDim.x * blockDim.x) {
+    const int s = a.srcs[i];
+    a.dist[s] = 0;
+    st_entry(a.far, (size_t)i, s, 0);
+    atomicMin(&c->far_min[0].v, bucket_of_key(a, bucket_key(a, s, 0u)));
+  }
+}
+
+__global__ void k_init_ctl(Args a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Ctl* c = a.ctl;
+  const unsigned b0 = c->far_min[0].v;
   c->c.cur = b0;
-  c->c.in_kind = kInWin;
-  c->c.in_index = slot;
-  c->c.in_count = 1;
+  c->c.in_kind = kInFar;
+  c->c.in_index = 0;
+  c->c.in_count = (unsigned)a.nsrc;
+  c->c.far_in = 0;
   c->c.win_hi = sat_add(b0, (unsigned)a.K);
   c->c.buckets = 1;
-  c->win_tail[slot].v = 1;
-  c->far_min[0].v = c->far_min[1].v = kNoBucket;
-  c->need.v = 1;
-  st_entry(a.win, (size_t)slot * a.cap, src, 0);
+  c->far_tail[0].v = (unsigned)a.nsrc;
+  c->far_min[1].v = kNoBucket;
+  c->need.v = (unsigned)a.nsrc;
+}
+
+__global__ void k_far_min_init(Ctl* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c->far_min[0].v = kNoBucket;
 }
 
 __global__ __launch_bounds__(kBlock) void k_validate(const int* w, long long m, Ctl* ctl) {
@@ -696,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   __syncthreads();
   while (!s.done) {
     run_round(a, s, c);
-    round_barrier(a, s, true);
+    round_barrier(a, s, c, true);
     if (threadIdx.x == 0) load_control(a, s);
     __syncthreads();
   }
@@ -712,35 +815,39 @@ __global__ __launch_bounds__(kBlock) void k_round(Args a) {
   __syncthreads();
   if (s.done) return;
   run_round(a, s, c);
-  round_barrier(a, s, false);
+  round_barrier(a, s, c, false);
   flush_counters(a, c);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill(int* p, int n, int value) {
+__global__ __launch_bounds__(kBlock) void k_fill(int* p, long long n, int value) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) p[v] = value;
 }
 
-// Canonical predecessors: for every edge (u,v) with dist[u] finite and
-// dist[u] + w == dist[v], pred[v] = min(pred[v], u).  One wavefront per
-// chunk of 64 consecutive source vertices walks the chunk's contiguous edge
-// range with coalesced loads; each edge finds its source lane by a binary
-// search over the lanes' row offsets.  Also counts reached vertices/edges.
-// pred == nullptr: counts only.
+// Canonical predecessors: for every edge (u,v) of every query copy with
+// dist[u] finite and dist[u] + w == dist[v], pred[v] = min(pred[v], u) (base
+// vertex ids).  One wavefront per chunk of 64 consecutive source vertices of
+// one copy walks the chunk's contiguous edge range with coalesced loads;
+// each edge finds its source lane by a binary search over the lanes' row
+// offsets.  Also counts reached vertices and edges.  pred == nullptr:
+// counts only.
 __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
   const int lane = (int)lane_id();
   const long long nwave = (long long)gridDim.x * (kBlock / kWave);
+  const long long per_copy = ((long long)a.nbase + kWave - 1) / kWave;
+  const long long chunks = per_copy * a.reps;
   unsigned long long rv = 0, re = 0;
-  for (long long ch = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; ch * kWave < a.n;
-       ch += nwave) {
-    const long long v0 = ch * kWave;
+  for (long long ch = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; ch < chunks; ch += nwave) {
+    const long long q = ch / per_copy;
+    const long long voff = q * a.nbase;
+    const long long v0 = (ch - q * per_copy) * kWave;
     const long long v = v0 + lane;
-    const long long vend = v0 + kWave < a.n ? v0 + kWave : a.n;
+    const long long vend = v0 + kWave < a.nbase ? v0 + kWave : a.nbase;
     const long long e0 = a.row_ptr[v0];
     const long long e1 = a.row_ptr[vend];
-    const int rs = v < a.n ? (int)(a.row_ptr[v] - e0) : (int)(e1 - e0);
-    const int dv = v < a.n ? a.dist[v] : kInf;
-    if (v < a.n && dv != kInf) {
+    const int rs = v < a.nbase ? (int)(a.row_ptr[v] - e0) : (int)(e1 - e0);
+    const int dv = v < a.nbase ? a.dist[voff + v] : kInf;
+    if (v < a.nbase && dv != kInf) {
       rv++;
       re += (unsigned long long)(a.row_ptr[v + 1] - a.row_ptr[v]);
     }
@@ -756,7 +863,7 @@ __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
       }
       const int du = __shfl(dv, lo);
       if (e < e1 && du != kInf) {
-        const int u = a.col[e];
+        const long long u = voff + a.col[e];
         const unsigned nd = (unsigned)du + (unsigned)a.w[e];
         if (nd == (unsigned)a.dist[u]) atomicMin(&pred[u], (int)(v0 + lo));
       }
@@ -772,11 +879,16 @@ __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pred_fix(int* pred, int n, int src) {
+__global__ __launch_bounds__(kBlock) void k_pred_fix(int* pred, long long n) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    if (v == src) pred[v] = src;
-    else if (pred[v] == kInf) pred[v] = -1;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    if (pred[v] == kInf) pred[v] = -1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pred_sources(Args a, int* pred) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.nsrc; i += gridDim.x * blockDim.x) {
+    const int s = a.srcs[i];
+    pred[s] = a.reps == 1 ? s : (int)((unsigned)s % (unsigned)a.nbase);
   }
 }
 
@@ -838,17 +950,31 @@ og_schedule resolved(const og_schedule* s) {
   return r;
 }
 
-long long queue_cap(const og_graph* g, const og_schedule* r) {
-  long long cap = r->queue_capacity > 0 ? r->queue_capacity : (long long)g->n + g->m / 8;
+// A call's shape: reps copies of the graph, nsrc sources, targets or not.
+struct Shape {
+  int reps;
+  int nsrc;
+  bool targets;
+};
+
+long long queue_cap(const og_graph* g, const og_schedule* r, const Shape& sh) {
+  long long cap = r->queue_capacity > 0 ? r->queue_capacity
+                                        : (long long)sh.reps * ((long long)g->n + g->m / 8) + sh.nsrc;
   if (cap < 1024) cap = 1024;
   if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+  if (cap < sh.nsrc) cap = sh.nsrc;  // the sources start in a far list
   return cap;
 }
 
-size_t ws_bytes_for(const og_graph* g, const og_schedule* r) {
-  const long long cap = queue_cap(g, r);
+size_t table_bytes(const Shape& sh) {
+  const size_t b = sizeof(int) * ((size_t)sh.nsrc + (sh.targets ? (size_t)sh.reps : 0));
+  return (b + 255) & ~(size_t)255;
+}
+
+size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
+  const long long cap = queue_cap(g, r, sh);
   const size_t lists = (size_t)r->window_buckets + 4;  // K window slots, 2 spill, 2 far
-  size_t b = kCtlBytes + lists * (size_t)cap * sizeof(int2);
+  size_t b = kCtlBytes + table_bytes(sh) + lists * (size_t)cap * sizeof(int2);
   return (b + 255) & ~(size_t)255;
 }
 
@@ -870,6 +996,11 @@ bool graph_ok(const og_graph* g) {
   return true;
 }
 
+bool shape_ok(const og_graph* g, const Shape& sh) {
+  if (sh.reps < 1 || sh.reps > kMaxQueries || sh.nsrc < 1 || sh.nsrc > 0x7fffffff / 2) return false;
+  return (long long)sh.reps * g->n < 0x7fffffffLL;
+}
+
 void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   if (!st) return;
   st->status = (og_status)h.status.v;
@@ -884,26 +1015,22 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   st->reached_vertices = (int64_t)h.st[kStReachedV].v;
   st->reached_edges = (int64_t)h.st[kStReachedE].v;
   st->queue_needed = (int64_t)h.need.v;
+  st->batches = (int64_t)h.st[kStBatches].v;
+  st->chain = (int64_t)h.st[kStChain].v;
 }
 
-og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, const og_schedule* sched,
-              int32_t* dist, int32_t* pred, void* ws, size_t ws_size, og_stats* stats, void* stream_v,
-              bool force_delta1) {
-  if (stats) std::memset(stats, 0, sizeof(*stats));
+// Common driver.  vsrcs: nsrc virtual source ids; vtgts: reps virtual
+// target ids or empty.  The caller has validated every argument.
+og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs, const std::vector<int>& vtgts,
+              const int32_t* h, const og_schedule* sched, int32_t* dist, int32_t* pred, void* ws, size_t ws_size,
+              og_stats* stats, void* stream_v, bool force_delta1) {
   auto fail = [&](og_status st) {
     if (stats) stats->status = st;
     return st;
   };
-  if (!graph_ok(g) || !schedule_ok(sched) || !dist || !ws) return fail(OG_ERR_INVALID_ARG);
-  if (src < 0 || src >= g->n) return fail(OG_ERR_INVALID_ARG);
-  if (dst != -1 && (dst < 0 || dst >= g->n)) return fail(OG_ERR_INVALID_ARG);
-  if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
   og_schedule r = resolved(sched);
   if (force_delta1) r.delta = 1;
-  if (ws_size < ws_bytes_for(g, &r)) {
-    if (stats) stats->queue_needed = 0;
-    return fail(OG_ERR_WORKSPACE);
-  }
+  if (ws_size < ws_bytes_for(g, &r, sh)) return fail(OG_ERR_WORKSPACE);
   hipStream_t stream = (hipStream_t)stream_v;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(OG_ERR_HIP);
@@ -917,22 +1044,27 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   if (nwg > kMaxWg) nwg = kMaxWg;
   if (nwg < 1) nwg = 1;
 
-  const long long cap = queue_cap(g, &r);
+  const long long cap = queue_cap(g, &r, sh);
   char* base = (char*)ws;
+  int* table = (int*)(base + kCtlBytes);
   Args a;
   a.row_ptr = (const long long*)g->row_ptr;
   a.col = g->col;
   a.w = g->w;
   a.dist = dist;
   a.h = h;
-  a.n = g->n;
-  a.target = dst;
+  a.nbase = g->n;
+  a.reps = sh.reps;
+  a.n = sh.reps * g->n;
+  a.srcs = table;
+  a.nsrc = sh.nsrc;
+  a.tgts = sh.targets ? table + sh.nsrc : nullptr;
   a.delta = (unsigned)r.delta;
   a.shift = -1;
   if ((r.delta & (r.delta - 1)) == 0) {
-    int sh = 0;
-    while ((1 << sh) < r.delta) sh++;
-    a.shift = sh;
+    int s = 0;
+    while ((1 << s) < r.delta) s++;
+    a.shift = s;
   }
   a.K = r.window_buckets;
   a.cap = (unsigned)cap;
@@ -941,15 +1073,30 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   a.max_rounds = (unsigned)r.max_rounds;
   a.nwg = nwg;
   a.ctl = (Ctl*)base;
-  a.win = (int2*)(base + kCtlBytes);
+  a.win = (int2*)(base + kCtlBytes + table_bytes(sh));
   a.spill = a.win + (size_t)a.K * (size_t)cap;
   a.far = a.spill + 2 * (size_t)cap;
 
   const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
   if (timing) (void)hipEventRecord(t_timers.ev[0], stream);
+  // query table: sources then targets, carried in kernel arguments
+  {
+    std::vector<int> all(vsrcs);
+    all.insert(all.end(), vtgts.begin(), vtgts.end());
+    for (size_t off = 0; off < all.size(); off += kTableChunk) {
+      TableChunk tc;
+      tc.offset = (int)off;
+      tc.count = (int)std::min<size_t>(kTableChunk, all.size() - off);
+      std::memcpy(tc.vals, all.data() + off, sizeof(int) * (size_t)tc.count);
+      hipLaunchKernelGGL(k_put_table, dim3(1), dim3(kBlock), 0, stream, table, tc);
+    }
+  }
   const int fill_grid = di.cus * 8;
-  hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, src);
-  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a, src);
+  const int src_grid = (sh.nsrc + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a);
+  hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
+  hipLaunchKernelGGL(k_init_sources, dim3(src_grid), dim3(kBlock), 0, stream, a);
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);
   if (r.flags & OG_FLAG_VALIDATE)
     hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
@@ -980,9 +1127,10 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   }
   if (timing) (void)hipEventRecord(t_timers.ev[2], stream);
   if (pred) {
-    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, g->n, kInf);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n, kInf);
     hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
-    hipLaunchKernelGGL(k_pred_fix, dim3(fill_grid), dim3(kBlock), 0, stream, pred, g->n, src);
+    hipLaunchKernelGGL(k_pred_fix, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n);
+    hipLaunchKernelGGL(k_pred_sources, dim3(src_grid), dim3(kBlock), 0, stream, a, pred);
   } else if (stats) {
     hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
   }
@@ -1006,11 +1154,41 @@ og_status run(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, con
   return (og_status)hc.status.v;
 }
 
+// Argument checks shared by every entry point (nothing is launched on
+// failure).  srcs / dsts are host arrays of base vertex ids.
+og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, const int32_t* dsts, int32_t reps,
+                      bool multi, const int32_t* h, bool need_h, const og_schedule* s, int32_t* dist, int32_t* pred,
+                      void* ws, size_t ws_bytes, og_stats* stats, void* stream, bool force_delta1) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  auto fail = [&](og_status st) {
+    if (stats) stats->status = st;
+    return st;
+  };
+  if (!graph_ok(g) || !schedule_ok(s) || !dist || !ws || !srcs) return fail(OG_ERR_INVALID_ARG);
+  if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
+  if (need_h && !h) return fail(OG_ERR_INVALID_ARG);
+  const Shape sh{reps, nsrc, dsts != nullptr};
+  if (!shape_ok(g, sh)) return fail(OG_ERR_INVALID_ARG);
+  std::vector<int> vs((size_t)nsrc), vt;
+  for (int i = 0; i < nsrc; ++i) {
+    if (srcs[i] < 0 || srcs[i] >= g->n) return fail(OG_ERR_INVALID_ARG);
+    vs[i] = multi ? srcs[i] : i * g->n + srcs[i];
+  }
+  if (dsts) {
+    vt.resize((size_t)reps);
+    for (int q = 0; q < reps; ++q) {
+      if (dsts[q] < 0 || dsts[q] >= g->n) return fail(OG_ERR_INVALID_ARG);
+      vt[q] = q * g->n + dsts[q];
+    }
+  }
+  return run(g, sh, vs, vt, h, s, dist, pred, ws, ws_bytes, stats, stream, force_delta1);
+}
+
 }  // namespace og
 
 extern "C" {
 
-int32_t og_version(void) { return (1 << 16) | 0; }
+int32_t og_version(void) { return (1 << 16) | 1; }
 
 const char* og_status_string(og_status s) {
   switch (s) {
@@ -1036,38 +1214,78 @@ og_status og_default_schedule(og_schedule* s) {
   return OG_OK;
 }
 
-size_t og_workspace_bytes(const og_graph* g, const og_schedule* s) {
-  if (!og::graph_ok(g) || !og::schedule_ok(s)) return 0;
+static size_t ws_bytes_shape(const og_graph* g, const og_schedule* s, const og::Shape& sh) {
+  if (!og::graph_ok(g) || !og::schedule_ok(s) || !og::shape_ok(g, sh)) return 0;
   og_schedule r = og::resolved(s);
-  return og::ws_bytes_for(g, &r);
+  return og::ws_bytes_for(g, &r, sh);
+}
+
+size_t og_workspace_bytes(const og_graph* g, const og_schedule* s) {
+  return ws_bytes_shape(g, s, og::Shape{1, 1, true});
+}
+
+size_t og_workspace_bytes_batch(const og_graph* g, const og_schedule* s, int32_t nq) {
+  return ws_bytes_shape(g, s, og::Shape{nq, nq, true});
+}
+
+size_t og_workspace_bytes_multi(const og_graph* g, const og_schedule* s, int32_t nsrc) {
+  return ws_bytes_shape(g, s, og::Shape{1, nsrc, false});
 }
 
 og_status og_sssp(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
                   void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
-  return og::run(g, src, -1, nullptr, s, dist, pred, ws, ws_bytes, stats, stream, false);
+  return og::checked_run(g, &src, 1, nullptr, 1, false, nullptr, false, s, dist, pred, ws, ws_bytes, stats, stream,
+                         false);
 }
 
 og_status og_wbfs(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
                   void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
-  return og::run(g, src, -1, nullptr, s, dist, pred, ws, ws_bytes, stats, stream, true);
+  return og::checked_run(g, &src, 1, nullptr, 1, false, nullptr, false, s, dist, pred, ws, ws_bytes, stats, stream,
+                         true);
 }
 
 og_status og_ppsp(const og_graph* g, int32_t src, int32_t dst, const og_schedule* s, int32_t* dist,
                   int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
-  if (dst < 0) {
-    if (stats) std::memset(stats, 0, sizeof(*stats)), stats->status = OG_ERR_INVALID_ARG;
-    return OG_ERR_INVALID_ARG;
-  }
-  return og::run(g, src, dst, nullptr, s, dist, pred, ws, ws_bytes, stats, stream, false);
+  return og::checked_run(g, &src, 1, &dst, 1, false, nullptr, false, s, dist, pred, ws, ws_bytes, stats, stream,
+                         false);
 }
 
 og_status og_astar(const og_graph* g, int32_t src, int32_t dst, const int32_t* h, const og_schedule* s,
                    int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
-  if (dst < 0 || !h) {
+  return og::checked_run(g, &src, 1, &dst, 1, false, h, true, s, dist, pred, ws, ws_bytes, stats, stream, false);
+}
+
+og_status og_sssp_batch(const og_graph* g, const int32_t* srcs, int32_t nq, const og_schedule* s, int32_t* dist,
+                        int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
+  return og::checked_run(g, srcs, nq, nullptr, nq, false, nullptr, false, s, dist, pred, ws, ws_bytes, stats,
+                         stream, false);
+}
+
+og_status og_ppsp_batch(const og_graph* g, const int32_t* srcs, const int32_t* dsts, int32_t nq,
+                        const og_schedule* s, int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes,
+                        og_stats* stats, void* stream) {
+  if (!dsts) {
     if (stats) std::memset(stats, 0, sizeof(*stats)), stats->status = OG_ERR_INVALID_ARG;
     return OG_ERR_INVALID_ARG;
   }
-  return og::run(g, src, dst, h, s, dist, pred, ws, ws_bytes, stats, stream, false);
+  return og::checked_run(g, srcs, nq, dsts, nq, false, nullptr, false, s, dist, pred, ws, ws_bytes, stats, stream,
+                         false);
+}
+
+og_status og_astar_batch(const og_graph* g, const int32_t* srcs, const int32_t* dsts, int32_t nq, const int32_t* h,
+                         const og_schedule* s, int32_t* dist, int32_t* pred, void* ws, size_t ws_bytes,
+                         og_stats* stats, void* stream) {
+  if (!dsts) {
+    if (stats) std::memset(stats, 0, sizeof(*stats)), stats->status = OG_ERR_INVALID_ARG;
+    return OG_ERR_INVALID_ARG;
+  }
+  return og::checked_run(g, srcs, nq, dsts, nq, false, h, true, s, dist, pred, ws, ws_bytes, stats, stream, false);
+}
+
+og_status og_sssp_multi(const og_graph* g, const int32_t* srcs, int32_t nsrc, const og_schedule* s, int32_t* dist,
+                        int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
+  return og::checked_run(g, srcs, nsrc, nullptr, 1, true, nullptr, false, s, dist, pred, ws, ws_bytes, stats, stream,
+                         false);
 }
 
 og_status og_read_stats(const void* ws, og_stats* stats, void* stream) {

@@ -70,7 +70,7 @@ def test_workspace_bytes():
     b = lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s))
     assert b % 256 == 0 and b >= 65536 + (16 + 4) * 1024 * 8
     s2 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000).to_c()
-    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 65536 + 12 * 5000 * 8
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 65536 + 256 + 12 * 5000 * 8
     bad = og.Schedule(delta=0).to_c()
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
     g0 = _lib.OgGraph(0, 0, 0x1000, None, None)
