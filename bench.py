@@ -81,6 +81,173 @@ def summarize_rocpd(db: str, counter: str | None) -> int:
     return 0
 
 
+def _line(metric, value, unit, steps, warmup, ms_per_step, config, **extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": "int32", "data": "synthetic", "config": config}
+    d.update(extra)
+    return json.dumps(d)
+
+
+def workload_rmat(args) -> int:
+    """R-MAT 24 (edge factor 16): SSSP (w in [1,1000)) and wBFS (w in [1,24))
+    per source, GTEPS = reached edges / query time; full parity of one source
+    against the CPU oracle."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1911_07260_amd as og
+    dev = torch.device("cuda:0")
+    g = gg.rmat(args.scale, 16, seed=0)
+    srcs = [int(x) for x in gg.pick_sources(g, 4, seed=2)]
+    dg = og.DeviceGraph.from_host(g, dev)
+    ws = og.Workspace(dev)
+    out = {}
+    for name, graph_w, fn, sched in (
+            ("sssp", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_EAGER_NO_FUSION,
+                                                flags=og.OG_FLAG_TIMING)),
+            ("sssp_fused", None, og.sssp, og.Schedule(delta=args.rmat_delta, flags=og.OG_FLAG_TIMING)),
+            ("wbfs", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING))):
+        gx = dg if graph_w is None else og.DeviceGraph(dg.row_ptr, dg.col, torch.from_numpy(
+            np.ascontiguousarray(graph_w, dtype=np.int32)).to(dev))
+        fn(gx, srcs[0], sched, ws=ws)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sts = [fn(gx, s, sched, ws=ws)[2] for s in srcs]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / len(srcs) * 1e3
+        e = float(np.mean([x["reached_edges"] for x in sts]))
+        out[name] = {"ms_per_query": round(ms, 3), "gteps": round(e / (ms * 1e-3) / 1e9, 4),
+                     "engine_ms": round(float(np.mean([x["engine_ms"] for x in sts])), 3),
+                     "relaxations": int(np.mean([x["relaxations"] for x in sts])), "rounds": int(np.mean(
+                         [x["rounds"] for x in sts]))}
+        print(f"[bench] rmat {name}: {ms:.2f} ms/query", file=sys.stderr, flush=True)
+    parity = None
+    if not args.no_cpu:
+        import oracle
+        d, p, _ = og.sssp(dg, srcs[0], og.Schedule(delta=args.rmat_delta, update=og.OG_EAGER_NO_FUSION), ws=ws)
+        rd, rp = oracle.get().sssp(g, srcs[0])
+        parity = bool(np.array_equal(d.cpu().numpy(), rd) and np.array_equal(p.cpu().numpy(), rp))
+    print(_line("GTEPS, SSSP on R-MAT", out["sssp"]["gteps"], "GTEPS", len(srcs), 1, out["sssp"]["ms_per_query"],
+                {"workload": f"R-MAT scale {args.scale}, edge factor 16 (0.57,0.19,0.19,0.05), symmetric, "
+                             f"w in [1,1000) (wBFS: [1,24)), 4 sources (seed 2)", "n": g.n, "m": g.m,
+                 "delta": args.rmat_delta, "update": "eager_no_fusion"},
+                results=out, parity_one_source=parity), flush=True)
+    return 0
+
+
+def workload_astar(args) -> int:
+    """Batched point-to-point A* on the road-like grid: `pairs` random
+    (s, t) pairs, estimate floor(10 * euclid), in launches of `batch` queries;
+    serial leg: the first `batch` pairs one query per launch."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1911_07260_amd as og
+    dev = torch.device("cuda:0")
+    g = gg.road(args.side, seed=0)
+    dg = og.DeviceGraph.from_host(g, dev)
+    P = args.pairs
+    srcs = gg.pick_sources(g, P, seed=3)
+    dsts = gg.pick_sources(g, P, seed=4)
+    sched = og.Schedule(delta=args.astar_delta, flags=og.OG_FLAG_TIMING,
+                        queue_capacity=max(1 << 22, args.batch * (1 << 20)))
+    ws = og.Workspace(dev)
+    B = args.batch
+    dist_t = np.empty(P, dtype=np.int64)
+    total_ms = 0.0
+    for b0 in range(0, P, B):
+        s_, t_ = srcs[b0:b0 + B], dsts[b0:b0 + B]
+        h = gg.grid_heuristic_device(args.side, t_, dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        d, _, st = og.astar_batch(dg, s_, t_, h, sched, pred=False, ws=ws)
+        torch.cuda.synchronize()
+        total_ms += (time.perf_counter() - t) * 1e3
+        dist_t[b0:b0 + len(s_)] = d[torch.arange(len(s_), device=dev), torch.as_tensor(t_, device=dev)].cpu().numpy()
+        del d, h
+    print(f"[bench] astar batched: {P} pairs in {total_ms:.1f} ms", file=sys.stderr, flush=True)
+    # serial: one query per launch for the first B pairs
+    ser = 0.0
+    for i in range(B):
+        h = gg.grid_heuristic_device(args.side, dsts[i:i + 1], dev)[0].contiguous()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        d, _, _ = og.astar(dg, int(srcs[i]), int(dsts[i]), h, og.Schedule(delta=args.astar_delta), pred=False, ws=ws)
+        torch.cuda.synchronize()
+        ser += (time.perf_counter() - t) * 1e3
+        assert int(d[int(dsts[i])].item()) == dist_t[i]
+    ser_per = ser / B
+    parity = None
+    if not args.no_cpu:
+        import oracle
+        orc = oracle.get()
+        k = min(6, P)
+        parity = all(orc.ppsp(g, int(srcs[i]), int(dsts[i])) == (dist_t[i] if dist_t[i] != og.INF else -1)
+                     for i in range(k))
+    per = total_ms / P
+    print(_line("A* queries/s, batched point-to-point on road-like grid", round(P / (total_ms * 1e-3), 2),
+                "queries/s", P, 0, round(per, 4),
+                {"workload": f"A* on road-like {args.side}x{args.side} grid, {P} random (s,t) pairs (seeds 3, 4), "
+                             f"h = floor(10*euclid), {B} queries per launch", "delta": args.astar_delta},
+                ms_per_query_batched=round(per, 4), ms_per_query_serial=round(ser_per, 4),
+                batched_vs_serial=round(ser_per / per, 2), parity_sample=parity), flush=True)
+    return 0
+
+
+def workload_rgg(args) -> int:
+    """Many uneven random geometric graphs in one launch (multi-source SSSP
+    over their block-diagonal union, one source per graph) vs one launch per
+    graph."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1911_07260_amd as og
+    dev = torch.device("cuda:0")
+    fam = gg.rgg_family(args.graphs, seed=5)
+    u, offs = gg.block_diagonal(fam)
+    loc = [int(gg.uniform(6 + i, gg.STREAM_SOURCES, 1, p.n)[0]) for i, p in enumerate(fam)]
+    srcs = [int(o) + s for o, s in zip(offs, loc)]
+    du = og.DeviceGraph.from_host(u, dev)
+    sched = og.Schedule(delta=args.rgg_delta, flags=og.OG_FLAG_TIMING)
+    ws = og.Workspace(dev)
+    og.sssp_multi(du, srcs, sched, ws=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    d, p, st = og.sssp_multi(du, srcs, sched, ws=ws)
+    torch.cuda.synchronize()
+    bms = (time.perf_counter() - t) * 1e3
+    # serial: one launch per graph (graphs uploaded beforehand)
+    dgs = [og.DeviceGraph.from_host(gp, dev) for gp in fam]
+    og.sssp(dgs[0], loc[0], og.Schedule(delta=args.rgg_delta), ws=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for gp, s in zip(dgs, loc):
+        og.sssp(gp, s, og.Schedule(delta=args.rgg_delta), ws=ws)
+    torch.cuda.synchronize()
+    sms = (time.perf_counter() - t) * 1e3
+    parity = None
+    if not args.no_cpu:
+        import oracle
+        orc = oracle.get()
+        dn = d.cpu().numpy()
+        parity = True
+        for i in range(0, len(fam), max(1, len(fam) // 8)):
+            rd, _ = orc.sssp(fam[i], loc[i])
+            parity &= bool(np.array_equal(dn[offs[i]:offs[i] + fam[i].n], rd))
+    print(_line("GTEPS, many uneven random geometric graphs in one launch", round(
+        st["reached_edges"] / (bms * 1e-3) / 1e9, 4), "GTEPS", 1, 1, round(bms, 3),
+                {"workload": f"{args.graphs} RGGs, n log-uniform in [1000, 64000], mean degree 6, "
+                             f"w = max(1, llround(length)), one source each", "n": u.n, "m": u.m,
+                 "delta": args.rgg_delta},
+                ms_batched=round(bms, 3), ms_serial=round(sms, 3), batched_vs_serial=round(sms / bms, 2),
+                rounds=st["rounds"], parity_sample=parity), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,12 +259,26 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the unfused / host-driven legs")
     ap.add_argument("--cpu-sources", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=64, help="queries per launch in the batched leg")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-rocpd", metavar="DB")
     ap.add_argument("--counter")
+    ap.add_argument("--workload", default="road", choices=["road", "rmat", "astar", "rgg"],
+                    help="road (default, the headline line) or one of the extra workloads")
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--rmat-delta", type=int, default=32)
+    ap.add_argument("--pairs", type=int, default=4096)
+    ap.add_argument("--astar-delta", type=int, default=512)
+    ap.add_argument("--graphs", type=int, default=1024)
+    ap.add_argument("--rgg-delta", type=int, default=4096)
     args = ap.parse_args()
     if args.summarize_rocpd:
         return summarize_rocpd(args.summarize_rocpd, args.counter)
+    if args.workload != "road":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            return 2
+        return {"rmat": workload_rmat, "astar": workload_astar, "rgg": workload_rgg}[args.workload](args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design is described in "
@@ -191,7 +372,25 @@ def main() -> int:
                              "rounds": int(np.mean([s["rounds"] for s in stats]))}
         variants["fused_vs_unfused_speedup"] = round(
             variants["unfused_persistent"]["engine_ms"] / engine_ms, 2)
-        variants["batched_vs_serial"] = None  # multi-query batching is not built yet
+        # batched: nq queries (the same 8 sources repeated, then fresh ones)
+        # in one persistent launch, distances and predecessors for all
+        nq = args.batch
+        bsrcs = [int(s) for s in gg.pick_sources(g, nq, seed=1)]
+        bsched = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING,
+                             queue_capacity=max(1 << 22, nq * (1 << 21)))
+        bws = og.Workspace(dev)
+        og.sssp_batch(dg, bsrcs, bsched, ws=bws)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bd, bp, bst = og.sssp_batch(dg, bsrcs, bsched, ws=bws)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - t) * 1e3
+        variants["batched"] = {"queries": nq, "ms_total": round(bms, 3), "ms_per_query": round(bms / nq, 3),
+                               "gteps": round(bst["reached_edges"] / (bms * 1e-3) / 1e9, 4),
+                               "engine_ms": round(bst["engine_ms"], 3), "rounds": bst["rounds"]}
+        variants["batched_vs_serial"] = round((wall / args.steps * 1e3) / (bms / nq), 2)
+        print(f"[bench] batched {nq} queries: {bms:.1f} ms ({bms / nq:.2f} ms/query)", file=sys.stderr, flush=True)
+        del bd, bp, bws
 
     cpu = None
     parity = None

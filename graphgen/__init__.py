@@ -181,3 +181,45 @@ def from_edges(n: int, src, dst, w, name: str = "edges") -> Graph:
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     return Graph(n=n, row_ptr=row_ptr, col=dst.astype(np.int32), w=w.astype(np.int32), name=name)
+
+
+def grid_heuristic_device(side: int, targets, device="cuda"):
+    """A* estimates for a batch of targets on a side x side grid, computed on
+    the device: [len(targets), side*side] int32, h_q[v] = floor(10 *
+    euclid(v, t_q)) evaluated in float64.  Distances are integers and every
+    edge weight is at least ceil(10 * length), so even a last-bit rounding
+    up in the device square root keeps h admissible."""
+    import torch
+    t = torch.as_tensor(np.asarray(targets, dtype=np.int64), device=device)
+    v = torch.arange(side * side, device=device, dtype=torch.int64)
+    r, c = (v // side).to(torch.float64), (v % side).to(torch.float64)
+    rt, ct = (t // side).to(torch.float64)[:, None], (t % side).to(torch.float64)[:, None]
+    h = torch.floor(10.0 * torch.sqrt((r[None, :] - rt) ** 2 + (c[None, :] - ct) ** 2))
+    return h.to(torch.int32).contiguous()
+
+
+def block_diagonal(graphs, name: str = "union") -> "tuple[Graph, np.ndarray]":
+    """Disjoint union of CSR graphs; returns (union, vertex offsets)."""
+    offs = np.zeros(len(graphs), dtype=np.int64)
+    n = 0
+    for i, g in enumerate(graphs):
+        offs[i] = n
+        n += g.n
+    row_ptr = [np.zeros(1, dtype=np.int64)]
+    cols, ws = [], []
+    eoff = 0
+    for g, o in zip(graphs, offs):
+        row_ptr.append(g.row_ptr[1:] + eoff)
+        cols.append(g.col.astype(np.int64) + o)
+        ws.append(g.w)
+        eoff += g.m
+    return Graph(n=n, row_ptr=np.concatenate(row_ptr), col=np.concatenate(cols).astype(np.int32),
+                 w=np.concatenate(ws).astype(np.int32), name=name), offs
+
+
+def rgg_family(count: int, nmin: int = 1000, nmax: int = 64000, mean_degree: float = 6.0, seed: int = 0):
+    """`count` random geometric graphs with sizes log-uniform in [nmin, nmax]
+    (graph i uses seed `seed*100003 + i`); returns the list of graphs."""
+    u = uniform(seed, STREAM_PAIRS, count, 1 << 30) / float(1 << 30)
+    sizes = np.exp(np.log(nmin) + u * (np.log(nmax) - np.log(nmin))).astype(np.int64)
+    return [rgg(int(sz), mean_degree, seed=seed * 100003 + i)[0] for i, sz in enumerate(sizes)]

@@ -1,0 +1,157 @@
+"""Schedule autotuner for the bucket engine.
+
+The paper tunes its schedules with an ensemble search (section 5.3, OpenTuner
+with an area-under-curve bandit) over the scheduling-language options.  This
+is a smaller, deterministic search written for this engine: every candidate
+is run through the C ABI on a few sample queries and timed with the
+library's HIP events (`OG_FLAG_TIMING`, bucket-engine time only); the search
+is
+
+  1. Delta on a coarse power-of-two ladder around the weight scale, with
+     and without bucket fusion (the two update strategies of section 4.2);
+  2. the fusion threshold and the window size around the best candidate;
+  3. Delta refined by factors of sqrt(2) around the best value;
+  4. the workgroup count.
+
+Each stage keeps the best candidate (lowest median engine time).  Results
+are returned as a `Schedule` plus a log of every candidate tried and can be
+saved as JSON.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+from dataclasses import asdict, dataclass, field
+
+import numpy as np
+import torch
+
+from . import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_TIMING, DeviceGraph, Schedule, Workspace, astar_batch,
+               ppsp_batch, sssp, sssp_batch)
+
+
+@dataclass
+class Trial:
+    schedule: dict
+    engine_ms: float
+    ok: bool
+
+
+@dataclass
+class TuneResult:
+    best: Schedule
+    best_ms: float
+    trials: list = field(default_factory=list)
+    seconds: float = 0.0
+
+    def to_json(self) -> str:
+        return json.dumps({"best": asdict(self.best), "best_ms": self.best_ms, "seconds": self.seconds,
+                           "trials": [asdict(t) for t in self.trials]}, indent=1)
+
+    def save(self, path: str) -> None:
+        with open(path, "w") as f:
+            f.write(self.to_json())
+
+
+class Autotuner:
+    """Times candidate schedules for one workload.
+
+    `runner(schedule) -> engine_ms` may be given directly; `for_sssp`,
+    `for_batch` and `for_ppsp_batch` build runners for the library's entry
+    points on sample sources.
+    """
+
+    def __init__(self, runner, base: Schedule | None = None, repeats: int = 1):
+        self.runner = runner
+        self.base = base or Schedule()
+        self.repeats = repeats
+        self.trials: list[Trial] = []
+        self._cache: dict = {}
+
+    # ---------------------------------------------------------- builders
+    @classmethod
+    def for_sssp(cls, graph: DeviceGraph, sources, **kw):
+        ws = Workspace(graph.device)
+
+        def run(s: Schedule) -> float:
+            t = []
+            for src in sources:
+                _, _, st = sssp(graph, int(src), s, pred=False, ws=ws)
+                t.append(st["engine_ms"])
+            return float(np.median(t))
+
+        return cls(run, **kw)
+
+    @classmethod
+    def for_batch(cls, graph: DeviceGraph, sources, **kw):
+        ws = Workspace(graph.device)
+
+        def run(s: Schedule) -> float:
+            _, _, st = sssp_batch(graph, sources, s, pred=False, ws=ws)
+            return float(st["engine_ms"])
+
+        return cls(run, **kw)
+
+    @classmethod
+    def for_ppsp_batch(cls, graph: DeviceGraph, sources, targets, h: torch.Tensor | None = None, **kw):
+        ws = Workspace(graph.device)
+
+        def run(s: Schedule) -> float:
+            if h is None:
+                _, _, st = ppsp_batch(graph, sources, targets, s, pred=False, ws=ws)
+            else:
+                _, _, st = astar_batch(graph, sources, targets, h, s, pred=False, ws=ws)
+            return float(st["engine_ms"])
+
+        return cls(run, **kw)
+
+    # ------------------------------------------------------------ search
+    def measure(self, s: Schedule) -> float:
+        key = tuple(sorted(asdict(s).items()))
+        if key in self._cache:
+            return self._cache[key]
+        s = Schedule(**{**asdict(s), "flags": s.flags | OG_FLAG_TIMING})
+        ms = []
+        ok = True
+        for _ in range(self.repeats):
+            try:
+                ms.append(self.runner(s))
+            except Exception:  # a schedule that overflows its queues is just a bad candidate
+                ok = False
+                break
+        val = float(np.median(ms)) if ok else math.inf
+        self._cache[key] = val
+        self.trials.append(Trial(asdict(s), val, ok))
+        return val
+
+    def _best(self, cands):
+        scored = [(self.measure(c), i, c) for i, c in enumerate(cands)]
+        scored.sort(key=lambda x: (x[0], x[1]))
+        return scored[0][2], scored[0][0]
+
+    def tune(self, weight_scale: float, hop_weight: float | None = None) -> TuneResult:
+        """weight_scale: a typical edge weight (e.g. the median); the Delta
+        ladder spans weight_scale/16 .. weight_scale*1024."""
+        t0 = time.perf_counter()
+        base = self.base
+        lo = max(1, int(weight_scale / 16))
+        deltas = sorted({1 << k for k in range(max(0, int(math.log2(lo))), int(math.log2(weight_scale * 1024)) + 1)})
+        cands = [Schedule(**{**asdict(base), "delta": d, "update": u})
+                 for d in deltas for u in (OG_EAGER_WITH_FUSION, OG_EAGER_NO_FUSION)]
+        best, best_ms = self._best(cands)
+        # threshold / window around the best
+        cands = [best]
+        if best.update == OG_EAGER_WITH_FUSION:
+            cands += [Schedule(**{**asdict(best), "fusion_threshold": t}) for t in (64, 256, 512)]
+        cands += [Schedule(**{**asdict(best), "window_buckets": k}) for k in (8, 32)]
+        best, best_ms = self._best(cands)
+        # refine Delta by sqrt(2)
+        cands = [best] + [Schedule(**{**asdict(best), "delta": max(1, int(round(best.delta * f)))})
+                          for f in (0.5, 0.7071, 1.4142, 2.0)]
+        best, best_ms = self._best(cands)
+        # workgroups
+        cands = [best] + [Schedule(**{**asdict(best), "workgroups": w}) for w in (256, 512, 1024)]
+        best, best_ms = self._best(cands)
+        best = Schedule(**{**asdict(best), "flags": base.flags})
+        return TuneResult(best=best, best_ms=best_ms, trials=list(self.trials), seconds=time.perf_counter() - t0)

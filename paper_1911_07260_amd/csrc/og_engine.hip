@@ -319,11 +319,10 @@ __device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v,
 //
 // from_lds: entries come from the local ring and carry their CSR row.  The
 // staleness check (d > dist[v]) is then made per edge, with the dist load
-// issued together with the edge loads, and no pre-load of dist[u] filters
-// the atomic minimum: a locally chased hop costs two dependent global round
-// trips (edge loads, then the atomic together with the next vertex's row).
-// Otherwise (a global list) the row is looked up per entry and a plain load
-// of dist[u] skips atomics that cannot succeed.
+// issued together with the edge loads; a small batch then needs two
+// dependent global round trips per hop (edge loads, then the atomic
+// together with the next vertex's row).  Otherwise (a global list) the row
+// is looked up per entry.
 __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds) {
   const int tid = threadIdx.x;
   const int v = ent.x, d = ent.y;
@@ -372,6 +371,11 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
   __syncthreads();
   const int nb = s.nb;
   const unsigned cur = s.cur;
+  // A plain load of dist[u] skips atomics that cannot succeed.  It costs a
+  // dependent round trip, so a small locally chased batch (latency-bound,
+  // one pass over its edges) goes straight to the atomic; larger batches
+  // (throughput-bound) filter.
+  const bool prefilter = !from_lds || total > kBlock;
   for (int base = 0; base < total; base += kBlock) {
     const int e = base + tid;
     bool has = false;
@@ -399,7 +403,7 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
       } else if (dsrc <= dnow) {
         const unsigned key = bucket_key(a, u, nd);
         bool go = !(a.tgts && key >= (unsigned)s.tb[query_of(a, u)]);  // cannot improve the target
-        if (go && !from_lds) go = (int)nd < a.dist[u];
+        if (go && prefilter) go = (int)nd < a.dist[u];
         if (go) {
           b = bucket_of_key(a, key);
           if (b < cur) b = cur;  // only an inconsistent A* estimate gets here

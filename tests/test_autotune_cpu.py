@@ -1,0 +1,37 @@
+"""The schedule search finds the optimum of a synthetic cost surface (no
+GPU: the runner is a plain function of the schedule)."""
+import math
+
+from paper_1911_07260_amd import OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, Schedule
+from paper_1911_07260_amd.autotune import Autotuner
+
+
+def cost(s: Schedule) -> float:
+    c = abs(math.log2(s.delta) - math.log2(724)) * 3.0        # best Delta ~ 724
+    c += 0.0 if s.update == OG_EAGER_WITH_FUSION else 5.0
+    c += {0: 0.5, 64: 2.0, 256: 0.0, 512: 0.3}.get(s.fusion_threshold, 1.0)
+    c += {0: 0.2, 8: 0.4, 32: 0.0}.get(s.window_buckets, 1.0)
+    c += {0: 0.0, 256: 1.0, 512: 0.5, 1024: 0.2}.get(s.workgroups, 1.0)
+    return 10.0 + c
+
+
+def test_search_finds_synthetic_optimum():
+    tuner = Autotuner(cost)
+    res = tuner.tune(weight_scale=15.0)
+    assert res.best.update == OG_EAGER_WITH_FUSION
+    assert res.best.fusion_threshold == 256
+    assert res.best.delta in (724, 512, 1024)
+    assert res.best_ms == min(t.engine_ms for t in res.trials)
+    assert len(res.trials) < 60
+    js = res.to_json()
+    assert '"best_ms"' in js
+
+
+def test_failing_candidates_are_skipped():
+    def runner(s):
+        if s.update == OG_EAGER_NO_FUSION:
+            raise RuntimeError("queue overflow")
+        return cost(s)
+    res = Autotuner(runner).tune(weight_scale=15.0)
+    assert res.best.update == OG_EAGER_WITH_FUSION
+    assert any(not t.ok for t in res.trials)
