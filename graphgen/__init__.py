@@ -223,3 +223,30 @@ def rgg_family(count: int, nmin: int = 1000, nmax: int = 64000, mean_degree: flo
     u = uniform(seed, STREAM_PAIRS, count, 1 << 30) / float(1 << 30)
     sizes = np.exp(np.log(nmin) + u * (np.log(nmax) - np.log(nmin))).astype(np.int64)
     return [rgg(int(sz), mean_degree, seed=seed * 100003 + i)[0] for i, sz in enumerate(sizes)]
+
+
+def _sm64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser on uint64 arrays (wrapping arithmetic)."""
+    x = x + np.uint64(0x9E3779B97F4A7C15)
+    x = (x ^ (x >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    x = (x ^ (x >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return x ^ (x >> np.uint64(31))
+
+
+STREAM_FLOAT_W = 104
+
+
+def float_weights(g: Graph, lo: float = 1.0, hi: float = 1000.0, seed: int = 3) -> np.ndarray:
+    """float32 weights, continuous uniform in [lo, hi), one draw per
+    undirected pair {u, v} (both directions equal): u01 of
+    sm64(sm64(sm64(seed) + stream) + min*n + max), scaled in float64 and
+    rounded to float32."""
+    with np.errstate(over="ignore"):
+        src = np.repeat(np.arange(g.n, dtype=np.uint64), g.degrees())
+        dst = g.col.astype(np.uint64)
+        a = np.minimum(src, dst)
+        b = np.maximum(src, dst)
+        key = _sm64(_sm64(np.array([seed], dtype=np.uint64))[0:1] + np.uint64(STREAM_FLOAT_W))[0]
+        x = _sm64(key + a * np.uint64(g.n) + b)
+    u = (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return (lo + (hi - lo) * u).astype(np.float32)

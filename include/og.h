@@ -205,6 +205,41 @@ size_t og_workspace_bytes_multi(const og_graph* g, const og_schedule* s, int32_t
 og_status og_sssp_multi(const og_graph* g, const int32_t* srcs, int32_t nsrc, const og_schedule* s, int32_t* dist,
                         int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream);
 
+/* ---- Real-valued weights (the differentiable variant) ------------------
+ * The same engine on float32 distances: every relaxation computes
+ * fl32(dist[u] + w) (round to nearest), so the result is the unique fixed
+ * point D(v) = min over in-edges fl32(D(u) + w(u,v)), D(src) = 0, whatever
+ * the schedule; unreachable vertices get +inf.  Weights must be finite and
+ * >= 0 (a NaN, infinite or negative weight is OG_ERR_NEGATIVE_WEIGHT); a sum
+ * that reaches +inf is OG_ERR_OVERFLOW.  Delta is the bucket width
+ * (bucket = floor(d / Delta)).  Predecessors follow the canonical rule with
+ * float32 tightness (fl32(D(u) + w) == D(v)); pred_edge[v] (optional, needs
+ * pred) is the CSR index of the tree edge pred[v] -> v, -1 for the source
+ * and unreachable vertices. */
+typedef struct og_graph_f32 {
+  int32_t n;
+  int64_t m;
+  const int64_t* row_ptr;  /* [n+1] */
+  const int32_t* col;      /* [m], rows sorted by destination */
+  const float* w;          /* [m] */
+} og_graph_f32;
+
+size_t og_workspace_bytes_f32(const og_graph_f32* g, const og_schedule* s);
+
+og_status og_sssp_f32(const og_graph_f32* g, int32_t src, const og_schedule* s, float* dist, int32_t* pred,
+                      int32_t* pred_edge, void* ws, size_t ws_bytes, og_stats* stats, void* stream);
+
+/* Backward pass: given the tree of an og_sssp_f32 call and an upstream
+ * gradient grad_dist[v] = dL/dD(v) (DEVICE, n floats), writes
+ * grad_w[e] = dL/dw_e (DEVICE, m floats): for the tree edge e into v, the
+ * sum of grad_dist over v's subtree (accumulated in float64, then rounded);
+ * 0 for every other edge.  This is the derivative of the distances when
+ * shortest paths are unique.  Stream-ordered, no synchronisation.
+ * Workspace: og_backward_workspace_bytes(n) bytes, 256-byte aligned. */
+size_t og_backward_workspace_bytes(int32_t n);
+og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const int32_t* pred_edge,
+                               const float* grad_dist, float* grad_w, void* ws, size_t ws_bytes, void* stream);
+
 /* Reads the status and counters of the last call made with workspace ws
  * (device) into *stats (host); used after an OG_FLAG_ASYNC call once the
  * stream has been synchronised.  Blocking copy on stream. */

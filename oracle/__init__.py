@@ -42,8 +42,8 @@ def build(out: str = _SO, mutation: int = 0) -> str:
     """Compile the oracle with gcc.  ``mutation`` > 0 plants one of the
     numbered bugs in ``oracle.c`` (used only by the pin tests, which must
     catch each of them)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", f"-DORACLE_MUTATION={int(mutation)}",
-           _SRC, "-o", out + ".tmp"]
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", f"-DORACLE_MUTATION={int(mutation)}",
+           _SRC, "-o", out + ".tmp", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out
@@ -68,6 +68,14 @@ def _bind(lib):
     lib.oracle_astar.argtypes = [i32, vp, vp, vp, i32, i32, vp, vp]
     lib.oracle_check.restype = ctypes.c_uint32
     lib.oracle_check.argtypes = [i32, vp, vp, vp, i32, vp, vp]
+    lib.oracle_dijkstra_f64.restype = ctypes.c_int
+    lib.oracle_dijkstra_f64.argtypes = [i32, vp, vp, vp, i32, vp]
+    lib.oracle_dijkstra_f32.restype = ctypes.c_int
+    lib.oracle_dijkstra_f32.argtypes = [i32, vp, vp, vp, i32, vp]
+    lib.oracle_tree_real.restype = ctypes.c_int
+    lib.oracle_tree_real.argtypes = [i32, vp, vp, vp, i32, vp, ctypes.c_int, vp, vp]
+    lib.oracle_subtree_grad.restype = ctypes.c_int
+    lib.oracle_subtree_grad.argtypes = [i32, i64, vp, vp, vp, vp, vp]
     return lib
 
 
@@ -149,6 +157,45 @@ class Oracle:
         if r < -1:
             raise ValueError("oracle_astar: bad arguments")
         return int(r), int(ex.value)
+
+    # ---- real-valued weights (float32 w) --------------------------------
+    def _csr_f(self, g, wf):
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(g.col, dtype=np.int32)
+        w = np.ascontiguousarray(wf, dtype=np.float32)
+        return rp, col, w
+
+    def dijkstra_real(self, g, wf, src: int, f32: bool) -> np.ndarray:
+        """Shortest distances (float64 array, inf unreachable): exact
+        arithmetic (f32=False) or every addition rounded to float32."""
+        rp, col, w = self._csr_f(g, wf)
+        d = np.empty(g.n, dtype=np.float64)
+        fn = self.lib.oracle_dijkstra_f32 if f32 else self.lib.oracle_dijkstra_f64
+        if fn(g.n, rp.ctypes.data, col.ctypes.data, w.ctypes.data, int(src), d.ctypes.data) != 0:
+            raise ValueError("oracle_dijkstra_real: bad arguments")
+        return d
+
+    def tree_real(self, g, wf, src: int, dist: np.ndarray, f32: bool):
+        """(pred, pred_edge) of the canonical tree (float32 or exact tightness)."""
+        rp, col, w = self._csr_f(g, wf)
+        dist = np.ascontiguousarray(dist, dtype=np.float64)
+        p = np.empty(g.n, dtype=np.int32)
+        pe = np.empty(g.n, dtype=np.int32)
+        self.lib.oracle_tree_real(g.n, rp.ctypes.data, col.ctypes.data, w.ctypes.data, int(src), dist.ctypes.data,
+                                  int(bool(f32)), p.ctypes.data, pe.ctypes.data)
+        return p, pe
+
+    def subtree_grad(self, g, dist, pred, pred_edge, upstream) -> np.ndarray:
+        """dL/dw for L = sum_v upstream[v] * D(v) on the given tree."""
+        dist = np.ascontiguousarray(dist, dtype=np.float64)
+        pred = np.ascontiguousarray(pred, dtype=np.int32)
+        pe = np.ascontiguousarray(pred_edge, dtype=np.int32)
+        up = np.ascontiguousarray(upstream, dtype=np.float64)
+        gw = np.empty(g.m, dtype=np.float64)
+        if self.lib.oracle_subtree_grad(g.n, g.m, dist.ctypes.data, pred.ctypes.data, pe.ctypes.data,
+                                        up.ctypes.data, gw.ctypes.data) != 0:
+            raise MemoryError("oracle_subtree_grad")
+        return gw
 
     def check(self, g, src: int, dist32: np.ndarray, pred: np.ndarray | None = None) -> int:
         """Bitmask of violated shortest-path certificate invariants."""

@@ -43,6 +43,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 #define ORACLE_INF INT64_MAX
 #define I32_INF 2147483647
@@ -362,4 +363,171 @@ uint32_t oracle_check(int32_t n, const int64_t* row_ptr, const int32_t* col, con
   }
   free(reached);
   return bad;
+}
+
+/* ---------------- real-valued weights (differentiable variant) ----------
+ * Weights are float32 values w >= 0.  Two oracles:
+ *
+ *  - oracle_dijkstra_f64: shortest distances in float64.  Every float32
+ *    weight has a 24-bit significand, and for weights in [2^-14, 2^10) and
+ *    distances below 2^30 every partial sum is a multiple of 2^-37 below
+ *    2^30, i.e. fits in 67 bits -- so beyond 2^53 the sums can round; for
+ *    the workloads used here (weights in (1, 1000), distances below 2^22,
+ *    ulp multiples of 2^-23) every sum is exact, and the result is the
+ *    exact real shortest distance.
+ *  - oracle_dijkstra_f32: the same search with every addition rounded to
+ *    float32 (d_new = fl32(d_u + w)).  Rounding is monotone, so the label
+ *    at each vertex converges to the unique fixed point
+ *    D(v) = min over in-edges fl32(D(u) + w), which is what any
+ *    label-correcting schedule computes in float32 arithmetic.
+ *
+ * Tree: pred[v] = smallest u with a tight edge (D(u) + w == D(v) in the
+ * arithmetic of the search); pred_edge[v] = that edge's index.  The
+ * gradient of L = sum_t D(t) (t over targets, with multiplicity) with
+ * respect to w_e is the number of targets in the subtree below e
+ * (unique shortest paths), computed by oracle_subtree_counts. */
+typedef struct {
+  double* key;
+  int32_t* vid;
+  int64_t size, cap;
+} dheap_t;
+
+static int dheap_push(dheap_t* h, double k, int32_t v) {
+  if (h->size == h->cap) {
+    int64_t nc = h->cap ? h->cap * 2 : 1024;
+    double* nk = (double*)realloc(h->key, sizeof(double) * (size_t)nc);
+    if (!nk) return 0;
+    h->key = nk;
+    int32_t* nv = (int32_t*)realloc(h->vid, sizeof(int32_t) * (size_t)nc);
+    if (!nv) return 0;
+    h->vid = nv;
+    h->cap = nc;
+  }
+  int64_t i = h->size++;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h->key[p] <= k) break;
+    h->key[i] = h->key[p];
+    h->vid[i] = h->vid[p];
+    i = p;
+  }
+  h->key[i] = k;
+  h->vid[i] = v;
+  return 1;
+}
+
+static void dheap_pop(dheap_t* h, double* k, int32_t* v) {
+  *k = h->key[0];
+  *v = h->vid[0];
+  double lk = h->key[--h->size];
+  int32_t lv = h->vid[h->size];
+  int64_t i = 0;
+  for (;;) {
+    int64_t c = 2 * i + 1;
+    if (c >= h->size) break;
+    if (c + 1 < h->size && h->key[c + 1] < h->key[c]) c++;
+    if (h->key[c] >= lk) break;
+    h->key[i] = h->key[c];
+    h->vid[i] = h->vid[c];
+    i = c;
+  }
+  h->key[i] = lk;
+  h->vid[i] = lv;
+}
+
+static volatile float f32_sink;
+/* float32 sum, rounded once (no excess precision or contraction) */
+static float add_f32(float a, float b) {
+  volatile float s = a + b;
+  return s;
+}
+
+static int dijkstra_real(int32_t n, const int64_t* row_ptr, const int32_t* col, const float* w, int32_t src,
+                         int use_f32, double* dist) {
+  if (n <= 0 || src < 0 || src >= n) return -1;
+  for (int32_t v = 0; v < n; ++v) dist[v] = INFINITY;
+  dheap_t h = {0, 0, 0, 0};
+  dist[src] = 0.0;
+  if (!dheap_push(&h, 0.0, src)) return -1;
+  while (h.size > 0) {
+    double d;
+    int32_t u;
+    dheap_pop(&h, &d, &u);
+    if (d > dist[u]) continue;
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      int32_t v = col[e];
+      double nd = use_f32 ? (double)add_f32((float)d, w[e]) : d + (double)w[e];
+      if (nd < dist[v]) {
+        dist[v] = nd;
+        if (!dheap_push(&h, nd, v)) { free(h.key); free(h.vid); return -1; }
+      }
+    }
+  }
+  free(h.key);
+  free(h.vid);
+  return 0;
+}
+
+int oracle_dijkstra_f64(int32_t n, const int64_t* row_ptr, const int32_t* col, const float* w, int32_t src,
+                        double* dist) {
+  return dijkstra_real(n, row_ptr, col, w, src, 0, dist);
+}
+
+int oracle_dijkstra_f32(int32_t n, const int64_t* row_ptr, const int32_t* col, const float* w, int32_t src,
+                        double* dist) {
+  return dijkstra_real(n, row_ptr, col, w, src, 1, dist);
+}
+
+/* Canonical tree from real distances: tightness in float32 arithmetic when
+ * use_f32, exact otherwise.  pred / pred_edge = -1 where unreachable;
+ * pred[src] = src, pred_edge[src] = -1. */
+int oracle_tree_real(int32_t n, const int64_t* row_ptr, const int32_t* col, const float* w, int32_t src,
+                     const double* dist, int use_f32, int32_t* pred, int32_t* pred_edge) {
+  if (n <= 0 || src < 0 || src >= n) return -1;
+  for (int32_t v = 0; v < n; ++v) { pred[v] = -1; pred_edge[v] = -1; }
+  for (int32_t u = 0; u < n; ++u) {
+    if (isinf(dist[u])) continue;
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      int32_t v = col[e];
+      if (v == src || isinf(dist[v])) continue;
+      double nd = use_f32 ? (double)add_f32((float)dist[u], w[e]) : dist[u] + (double)w[e];
+      if (nd == dist[v] && (pred[v] < 0 || u < pred[v])) { pred[v] = u; pred_edge[v] = (int32_t)e; }
+    }
+  }
+  pred[src] = src;
+  return 0;
+}
+
+/* grad_w[e] = sum of upstream[t] over vertices t in the subtree below tree
+ * edge e (0 for non-tree edges): the gradient of sum_t upstream[t] * D(t).
+ * Vertices are visited in decreasing distance, so every child is done
+ * before its parent. */
+static const double* g_sort_key;
+static int cmp_desc(const void* a, const void* b) {
+  double x = g_sort_key[*(const int32_t*)a], y = g_sort_key[*(const int32_t*)b];
+  return x < y ? 1 : (x > y ? -1 : 0);
+}
+
+int oracle_subtree_grad(int32_t n, int64_t m, const double* dist, const int32_t* pred, const int32_t* pred_edge,
+                        const double* upstream, double* grad_w) {
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  double* acc = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!order || !acc) { free(order); free(acc); return -1; }
+  int32_t k = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    acc[v] = upstream[v];
+    if (!isinf(dist[v])) order[k++] = v;
+  }
+  g_sort_key = dist;
+  qsort(order, (size_t)k, sizeof(int32_t), cmp_desc);
+  for (int64_t e = 0; e < m; ++e) grad_w[e] = 0.0;
+  for (int32_t i = 0; i < k; ++i) {
+    int32_t v = order[i];
+    if (pred_edge[v] < 0) continue;
+    grad_w[pred_edge[v]] = acc[v];
+    acc[pred[v]] += acc[v];
+  }
+  free(order);
+  free(acc);
+  return 0;
 }

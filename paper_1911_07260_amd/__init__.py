@@ -226,3 +226,6 @@ def sssp_multi(graph: DeviceGraph, srcs, schedule: Schedule | None = None, pred:
     s_ = _host_ids(srcs)
     return _call("og_sssp_multi", graph, [ctypes.c_void_p(s_.ctypes.data), len(s_)], schedule, pred, ws, stream,
                  multi=len(s_), **kw)
+
+
+from .diff import ShortestPathDistances, shortest_path_distances, sssp_backward_f32, sssp_f32  # noqa: E402

@@ -41,6 +41,16 @@ class OgGraph(ctypes.Structure):
     ]
 
 
+class OgGraphF32(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("m", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+    ]
+
+
 class OgSchedule(ctypes.Structure):
     _fields_ = [
         ("delta", ctypes.c_int32),
@@ -133,6 +143,14 @@ def load():
     lib.og_astar_batch.argtypes = [P(OgGraph), vp, vp, i32, vp] + common
     lib.og_sssp_multi.restype = i32
     lib.og_sssp_multi.argtypes = [P(OgGraph), vp, i32] + common
+    lib.og_workspace_bytes_f32.restype = ctypes.c_size_t
+    lib.og_workspace_bytes_f32.argtypes = [P(OgGraphF32), P(OgSchedule)]
+    lib.og_sssp_f32.restype = i32
+    lib.og_sssp_f32.argtypes = [P(OgGraphF32), i32, P(OgSchedule), vp, vp, vp, vp, ctypes.c_size_t, P(OgStats), vp]
+    lib.og_backward_workspace_bytes.restype = ctypes.c_size_t
+    lib.og_backward_workspace_bytes.argtypes = [i32]
+    lib.og_sssp_backward_f32.restype = i32
+    lib.og_sssp_backward_f32.argtypes = [P(OgGraphF32), vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.og_read_stats.restype = i32
     lib.og_read_stats.argtypes = [vp, P(OgStats), vp]
     _lib = lib

@@ -42,6 +42,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "og.h"
@@ -186,12 +187,6 @@ __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 __device__ __forceinline__ unsigned long long lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
-__device__ __forceinline__ unsigned bucket_key(const Args& a, int v, unsigned d) {
-  return a.h ? d + (unsigned)a.h[v] : d;  // both < 2^31: no wrap
-}
-__device__ __forceinline__ unsigned bucket_of_key(const Args& a, unsigned key) {
-  return a.shift >= 0 ? (key >> a.shift) : (key / a.delta);
-}
 // query (copy) of a virtual vertex
 __device__ __forceinline__ int query_of(const Args& a, int v) {
   return a.reps == 1 ? 0 : (int)((unsigned)v / (unsigned)a.nbase);
@@ -204,6 +199,65 @@ __device__ __forceinline__ unsigned sat_add(unsigned x, unsigned y) {
 __device__ __forceinline__ void set_status(Ctl* c, int st) {
   atomicCAS(reinterpret_cast<int*>(&c->status.v), 0, st);
 }
+
+// Distance arithmetic.  Distances are stored as int32 bit patterns so that
+// one 32-bit atomic minimum serves both kinds: non-negative int32 values, or
+// non-negative float32 values (whose bit patterns order like the floats,
+// with +inf = 0x7f800000 as the unreachable label).
+struct IntW {
+  static constexpr int kInfBits = INT_MAX;
+  // nd = d + w; false (and a status) for a negative weight or a sum that
+  // reaches INT32_MAX
+  __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
+    if (wraw < 0) {
+      set_status(a.ctl, OG_ERR_NEGATIVE_WEIGHT);
+      return false;
+    }
+    const unsigned sum = (unsigned)d + (unsigned)wraw;
+    if (sum >= (unsigned)INT_MAX) {
+      set_status(a.ctl, OG_ERR_OVERFLOW);
+      return false;
+    }
+    *nd = (int)sum;
+    return true;
+  }
+  __device__ static bool tight(int du, int wraw, int dv) { return (unsigned)du + (unsigned)wraw == (unsigned)dv; }
+  // priority of vertex v at distance d: d, or d + h[v] for A*
+  __device__ static unsigned key(const Args& a, int v, int d) {
+    return a.h ? (unsigned)d + (unsigned)a.h[v] : (unsigned)d;  // both < 2^31: no wrap
+  }
+  __device__ static unsigned bucket(const Args& a, unsigned key) {
+    return a.shift >= 0 ? (key >> a.shift) : (key / a.delta);
+  }
+};
+
+struct FloatW {
+  static constexpr int kInfBits = 0x7f800000;  // +inf
+  __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
+    const float w = __int_as_float(wraw);
+    if (!(w >= 0.0f) || w == __int_as_float(kInfBits)) {  // negative, NaN or infinite
+      set_status(a.ctl, OG_ERR_NEGATIVE_WEIGHT);
+      return false;
+    }
+    const float sum = __fadd_rn(__int_as_float(d), w);
+    if (sum == __int_as_float(kInfBits)) {
+      set_status(a.ctl, OG_ERR_OVERFLOW);
+      return false;
+    }
+    *nd = __float_as_int(sum);
+    return true;
+  }
+  __device__ static bool tight(int du, int wraw, int dv) {
+    return __fadd_rn(__int_as_float(du), __int_as_float(wraw)) == __int_as_float(dv);
+  }
+  __device__ static unsigned key(const Args&, int, int d) { return (unsigned)d; }
+  // floor(d / Delta): the float64 quotient of two float32 values never
+  // rounds across an integer, so this is the exact floor
+  __device__ static unsigned bucket(const Args& a, unsigned key) {
+    const double q = floor((double)__int_as_float((int)key) / (double)a.delta);
+    return q >= 4294967294.0 ? 4294967294u : (unsigned)q;
+  }
+};
 
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
   int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
@@ -323,6 +377,7 @@ __device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v,
 // dependent global round trips per hop (edge loads, then the atomic
 // together with the next vertex's row).  Otherwise (a global list) the row
 // is looked up per entry.
+template <class W>
 __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds) {
   const int tid = threadIdx.x;
   const int v = ent.x, d = ent.y;
@@ -340,10 +395,10 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
       const int cv = a.dist[v];
       const long long r0 = a.row_ptr[vb];
       const long long r1 = a.row_ptr[vb + 1];
-      const unsigned key = bucket_key(a, v, (unsigned)d);
+      const unsigned key = W::key(a, v, d);
       bool live = d <= cv;
       if (live) {
-        rb = bucket_of_key(a, key);
+        rb = W::bucket(a, key);
         if (rb > s.cur) {
           repush = true;  // a far-list entry that belongs to a later bucket
           live = false;
@@ -395,17 +450,14 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
       const int dnow = from_lds ? a.dist[s.bv[lo]] : dsrc;
       u = ub + s.bvo[lo];
       c.relax++;
-      nd = (unsigned)dsrc + (unsigned)wt;
-      if (wt < 0) {
-        set_status(a.ctl, OG_ERR_NEGATIVE_WEIGHT);
-      } else if (nd >= (unsigned)kInf) {
-        set_status(a.ctl, OG_ERR_OVERFLOW);
-      } else if (dsrc <= dnow) {
-        const unsigned key = bucket_key(a, u, nd);
+      int ndi = 0;
+      if (dsrc <= dnow && W::add(a, dsrc, wt, &ndi)) {
+        nd = (unsigned)ndi;
+        const unsigned key = W::key(a, u, ndi);
         bool go = !(a.tgts && key >= (unsigned)s.tb[query_of(a, u)]);  // cannot improve the target
         if (go && prefilter) go = (int)nd < a.dist[u];
         if (go) {
-          b = bucket_of_key(a, key);
+          b = W::bucket(a, key);
           if (b < cur) b = cur;  // only an inconsistent A* estimate gets here
           long long q0 = 0, q1 = 0;
           const bool chase = a.fused && b == cur;
@@ -461,6 +513,7 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
 // A round input that fits in one batch per workgroup is split statically
 // (workgroup b takes the b-th slice, no atomics); a larger one is handed
 // out in kBlock chunks through an atomic cursor.
+template <class W>
 __device__ void run_round(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
   const int2* in = list_ptr(a, s.in_kind, s.in_index);
@@ -523,7 +576,7 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
         ent = make_int4(e.x, e.y, 0, 0);
       }
     }
-    process_batch(a, s, c, ent, mode == 1);
+    process_batch<W>(a, s, c, ent, mode == 1);
     c.batches++;
     c.round_batches++;
   }
@@ -744,9 +797,9 @@ __global__ void k_put_table(int* table, TableChunk tc) {
   for (int i = threadIdx.x; i < tc.count; i += blockDim.x) table[tc.offset + i] = tc.vals[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_init(Args a) {
+__global__ __launch_bounds__(kBlock) void k_init(Args a, int inf_bits) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) a.dist[v] = kInf;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) a.dist[v] = inf_bits;
   // zero the control block (grid-stride over its words)
   unsigned* words = reinterpret_cast<unsigned*>(a.ctl);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (long long)(sizeof(Ctl) / 4); i += stride)
@@ -757,13 +810,14 @@ __global__ __launch_bounds__(kBlock) void k_init(Args a) {
 // smallest source bucket.  The first round is a far round: it processes the
 // sources of the smallest bucket and files the others (A* estimates can put
 // sources of different queries in different buckets).
+template <class W>
 __global__ __launch_bounds__(kBlock) void k_init_sources(Args a) {
   Ctl* c = a.ctl;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.nsrc; i += gridDim.x * blockDim.x) {
     const int s = a.srcs[i];
     a.dist[s] = 0;
     st_entry(a.far, (size_t)i, s, 0);
-    atomicMin(&c->far_min[0].v, bucket_of_key(a, bucket_key(a, s, 0u)));
+    atomicMin(&c->far_min[0].v, W::bucket(a, W::key(a, s, 0)));
   }
 }
 
@@ -796,13 +850,14 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* w, long long m, 
 
 // Persistent engine: one cooperative launch; rounds separated by a
 // device-wide barrier whose last arriver takes the bucket decision.
+template <class W>
 __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   __shared__ Smem s;
   Counters c;
   if (threadIdx.x == 0) load_control(a, s);
   __syncthreads();
   while (!s.done) {
-    run_round(a, s, c);
+    run_round<W>(a, s, c);
     round_barrier(a, s, c, true);
     if (threadIdx.x == 0) load_control(a, s);
     __syncthreads();
@@ -812,13 +867,14 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
 
 // Host-driven engine: one launch per round; the last workgroup to finish
 // takes the bucket decision for the next launch.
+template <class W>
 __global__ __launch_bounds__(kBlock) void k_round(Args a) {
   __shared__ Smem s;
   Counters c;
   if (threadIdx.x == 0) load_control(a, s);
   __syncthreads();
   if (s.done) return;
-  run_round(a, s, c);
+  run_round<W>(a, s, c);
   round_barrier(a, s, c, false);
   flush_counters(a, c);
 }
@@ -835,6 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(int* p, long long n, int value)
 // each edge finds its source lane by a binary search over the lanes' row
 // offsets.  Also counts reached vertices and edges.  pred == nullptr:
 // counts only.
+template <class W>
 __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
   const int lane = (int)lane_id();
   const long long nwave = (long long)gridDim.x * (kBlock / kWave);
@@ -850,8 +907,8 @@ __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
     const long long e0 = a.row_ptr[v0];
     const long long e1 = a.row_ptr[vend];
     const int rs = v < a.nbase ? (int)(a.row_ptr[v] - e0) : (int)(e1 - e0);
-    const int dv = v < a.nbase ? a.dist[voff + v] : kInf;
-    if (v < a.nbase && dv != kInf) {
+    const int dv = v < a.nbase ? a.dist[voff + v] : W::kInfBits;
+    if (v < a.nbase && dv != W::kInfBits) {
       rv++;
       re += (unsigned long long)(a.row_ptr[v + 1] - a.row_ptr[v]);
     }
@@ -866,10 +923,9 @@ __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
         if (r <= rel) lo += step;
       }
       const int du = __shfl(dv, lo);
-      if (e < e1 && du != kInf) {
+      if (e < e1 && du != W::kInfBits) {
         const long long u = voff + a.col[e];
-        const unsigned nd = (unsigned)du + (unsigned)a.w[e];
-        if (nd == (unsigned)a.dist[u]) atomicMin(&pred[u], (int)(v0 + lo));
+        if (W::tight(du, a.w[e], a.dist[u])) atomicMin(&pred[u], (int)(v0 + lo));
       }
     }
   }
@@ -896,11 +952,81 @@ __global__ __launch_bounds__(kBlock) void k_pred_sources(Args a, int* pred) {
   }
 }
 
+// Tree edge of every vertex from its (canonical) predecessor: the index of
+// the edge pred[v] -> v, found by binary search in pred[v]'s row (rows are
+// sorted by destination).  -1 for the source and unreachable vertices.
+__global__ __launch_bounds__(kBlock) void k_pred_edge_ids(Args a, const int* pred, int* pred_edge) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    const int p = pred[v];
+    int e = -1;
+    if (p >= 0 && p != (int)v) {
+      long long lo = a.row_ptr[p], hi = a.row_ptr[p + 1] - 1;
+      while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (a.col[mid] < (int)v) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo <= hi && a.col[lo] == (int)v) e = (int)lo;
+    }
+    pred_edge[v] = e;
+  }
+}
+
+// Backward pass of the differentiable search (reverse-topological subtree
+// sums over the shortest-path tree): grad_w[e] for the tree edge e into v
+// is the sum of grad_dist over v's subtree; non-tree edges get 0.  acc
+// (float64) and cnt (children not yet folded in) live in the workspace.
+__global__ __launch_bounds__(kBlock) void k_bw_init(const float* grad_dist, int n, float* grad_w, long long m,
+                                                     double* acc, int* cnt) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long v = t0; v < n; v += stride) {
+    acc[v] = (double)grad_dist[v];
+    cnt[v] = 0;
+  }
+  for (long long e = t0; e < m; e += stride) grad_w[e] = 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bw_count(const int* pred, const int* pred_edge, int n, int* cnt) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    if (pred_edge[v] >= 0) atomicAdd(&cnt[pred[v]], 1);
+}
+
+// Every leaf climbs towards the root, adding its subtree sum into its
+// parent; the child that folds in last (its decrement of the parent's
+// counter reaches zero) carries on from the parent, whose sum is then
+// complete.  Each addition finishes before the decrement that announces it
+// (wait on the returned value), so the last child reads the full sum.
+__global__ __launch_bounds__(kBlock) void k_bw_climb(const int* pred, const int* pred_edge, int n, float* grad_w,
+                                                      double* acc, int* cnt) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    if (pred_edge[v] < 0 || cnt[v] != 0) continue;  // not a leaf of the tree
+    int x = (int)v;
+    double val = acc[x];
+    for (;;) {
+      const int e = pred_edge[x];
+      if (e < 0) break;
+      grad_w[e] = (float)val;
+      const int p = pred[x];
+      const double before = atomicAdd(&acc[p], val);
+      wait_vm();
+      (void)before;
+      if (atomicSub(&cnt[p], 1) != 1) break;
+      x = p;
+      val = __hip_atomic_load(&acc[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ host
 
 struct DeviceInfo {
   int cus = 0;
-  int occ_persistent = 0;
+  int occ_int = 0;    // co-resident k_persistent<IntW> workgroups per CU
+  int occ_float = 0;  // co-resident k_persistent<FloatW> workgroups per CU
   int coop = 0;
   bool valid = false;
 };
@@ -915,8 +1041,9 @@ bool device_info(int dev, DeviceInfo* out) {
   if (!di.valid) {
     if (hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&di.coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return false;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_persistent, k_persistent, kBlock, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_int, k_persistent<IntW>, kBlock, 0) != hipSuccess)
+      return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_float, k_persistent<FloatW>, kBlock, 0) != hipSuccess)
       return false;
     di.valid = true;
   }
@@ -1025,9 +1152,10 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
 
 // Common driver.  vsrcs: nsrc virtual source ids; vtgts: reps virtual
 // target ids or empty.  The caller has validated every argument.
+template <class W>
 og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs, const std::vector<int>& vtgts,
-              const int32_t* h, const og_schedule* sched, int32_t* dist, int32_t* pred, void* ws, size_t ws_size,
-              og_stats* stats, void* stream_v, bool force_delta1) {
+              const int32_t* h, const og_schedule* sched, int32_t* dist, int32_t* pred, int32_t* pred_edge, void* ws,
+              size_t ws_size, og_stats* stats, void* stream_v, bool force_delta1) {
   auto fail = [&](og_status st) {
     if (stats) stats->status = st;
     return st;
@@ -1042,7 +1170,8 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   if (!device_info(dev, &di)) return fail(OG_ERR_HIP);
   const bool persistent = r.engine == OG_ENGINE_PERSISTENT;
   if (persistent && !di.coop) return fail(OG_ERR_HIP);
-  int maxwg = di.cus * (di.occ_persistent > 0 ? di.occ_persistent : 1);
+  const int occ = std::is_same<W, FloatW>::value ? di.occ_float : di.occ_int;
+  int maxwg = di.cus * (occ > 0 ? occ : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
   if (persistent && nwg > maxwg) nwg = maxwg;
   if (nwg > kMaxWg) nwg = kMaxWg;
@@ -1097,9 +1226,9 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   }
   const int fill_grid = di.cus * 8;
   const int src_grid = (sh.nsrc + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a);
+  hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int)W::kInfBits);
   hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
-  hipLaunchKernelGGL(k_init_sources, dim3(src_grid), dim3(kBlock), 0, stream, a);
+  hipLaunchKernelGGL(k_init_sources<W>, dim3(src_grid), dim3(kBlock), 0, stream, a);
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);
   if (r.flags & OG_FLAG_VALIDATE)
     hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
@@ -1108,7 +1237,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
 
   if (persistent) {
     void* kargs[] = {&a};
-    if (hipLaunchCooperativeKernel((const void*)k_persistent, dim3(nwg), dim3(kBlock), kargs, 0, stream) !=
+    if (hipLaunchCooperativeKernel((const void*)k_persistent<W>, dim3(nwg), dim3(kBlock), kargs, 0, stream) !=
         hipSuccess)
       return fail(OG_ERR_HIP);
   } else {
@@ -1119,7 +1248,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     long long launched = 0;
     const long long cap_launches = r.max_rounds > 0 ? (long long)r.max_rounds + group : (1LL << 40);
     while (!done && launched < cap_launches) {
-      for (int i = 0; i < group; ++i) hipLaunchKernelGGL(k_round, dim3(nwg), dim3(kBlock), 0, stream, a);
+      for (int i = 0; i < group; ++i) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a);
       launched += group;
       unsigned hd[64];  // the Control line and the status line
       if (hipMemcpyAsync(hd, a.ctl, sizeof(hd), hipMemcpyDeviceToHost, stream) != hipSuccess)
@@ -1132,11 +1261,12 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   if (timing) (void)hipEventRecord(t_timers.ev[2], stream);
   if (pred) {
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n, kInf);
-    hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
+    hipLaunchKernelGGL(k_pred_edges<W>, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
     hipLaunchKernelGGL(k_pred_fix, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n);
     hipLaunchKernelGGL(k_pred_sources, dim3(src_grid), dim3(kBlock), 0, stream, a, pred);
+    if (pred_edge) hipLaunchKernelGGL(k_pred_edge_ids, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, pred_edge);
   } else if (stats) {
-    hipLaunchKernelGGL(k_pred_edges, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
+    hipLaunchKernelGGL(k_pred_edges<W>, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
   }
   if (timing) (void)hipEventRecord(t_timers.ev[3], stream);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
@@ -1160,9 +1290,11 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
 
 // Argument checks shared by every entry point (nothing is launched on
 // failure).  srcs / dsts are host arrays of base vertex ids.
+template <class W = IntW>
 og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, const int32_t* dsts, int32_t reps,
                       bool multi, const int32_t* h, bool need_h, const og_schedule* s, int32_t* dist, int32_t* pred,
-                      void* ws, size_t ws_bytes, og_stats* stats, void* stream, bool force_delta1) {
+                      void* ws, size_t ws_bytes, og_stats* stats, void* stream, bool force_delta1,
+                      int32_t* pred_edge = nullptr) {
   if (stats) std::memset(stats, 0, sizeof(*stats));
   auto fail = [&](og_status st) {
     if (stats) stats->status = st;
@@ -1185,7 +1317,8 @@ og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, cons
       vt[q] = q * g->n + dsts[q];
     }
   }
-  return run(g, sh, vs, vt, h, s, dist, pred, ws, ws_bytes, stats, stream, force_delta1);
+  if (pred_edge && !pred) return fail(OG_ERR_INVALID_ARG);
+  return run<W>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
 }
 
 }  // namespace og
@@ -1290,6 +1423,46 @@ og_status og_sssp_multi(const og_graph* g, const int32_t* srcs, int32_t nsrc, co
                         int32_t* pred, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
   return og::checked_run(g, srcs, nsrc, nullptr, 1, true, nullptr, false, s, dist, pred, ws, ws_bytes, stats, stream,
                          false);
+}
+
+static_assert(sizeof(og_graph) == sizeof(og_graph_f32), "graph views share one layout");
+
+size_t og_workspace_bytes_f32(const og_graph_f32* g, const og_schedule* s) {
+  return ws_bytes_shape(reinterpret_cast<const og_graph*>(g), s, og::Shape{1, 1, false});
+}
+
+og_status og_sssp_f32(const og_graph_f32* g, int32_t src, const og_schedule* s, float* dist, int32_t* pred,
+                      int32_t* pred_edge, void* ws, size_t ws_bytes, og_stats* stats, void* stream) {
+  return og::checked_run<og::FloatW>(reinterpret_cast<const og_graph*>(g), &src, 1, nullptr, 1, false, nullptr, false,
+                                     s, reinterpret_cast<int32_t*>(dist), pred, ws, ws_bytes, stats, stream, false,
+                                     pred_edge);
+}
+
+size_t og_backward_workspace_bytes(int32_t n) {
+  if (n < 1) return 0;
+  const size_t b = sizeof(double) * (size_t)n + sizeof(int) * (size_t)n;
+  return (b + 255) & ~(size_t)255;
+}
+
+og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const int32_t* pred_edge,
+                               const float* grad_dist, float* grad_w, void* ws, size_t ws_bytes, void* stream) {
+  if (!og::graph_ok(reinterpret_cast<const og_graph*>(g)) || !pred || !pred_edge || !grad_dist || !grad_w || !ws)
+    return OG_ERR_INVALID_ARG;
+  if (((uintptr_t)ws & 255) != 0) return OG_ERR_INVALID_ARG;
+  if (ws_bytes < og_backward_workspace_bytes(g->n)) return OG_ERR_WORKSPACE;
+  int dev = 0;
+  og::DeviceInfo di;
+  if (hipGetDevice(&dev) != hipSuccess || !og::device_info(dev, &di)) return OG_ERR_HIP;
+  hipStream_t st = (hipStream_t)stream;
+  double* acc = (double*)ws;
+  int* cnt = (int*)((char*)ws + sizeof(double) * (size_t)g->n);
+  const int grid = di.cus * 8;
+  hipLaunchKernelGGL(og::k_bw_init, dim3(grid), dim3(og::kBlock), 0, st, grad_dist, g->n, grad_w, (long long)g->m,
+                     acc, cnt);
+  hipLaunchKernelGGL(og::k_bw_count, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, cnt);
+  hipLaunchKernelGGL(og::k_bw_climb, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, grad_w, acc, cnt);
+  if (hipGetLastError() != hipSuccess) return OG_ERR_HIP;
+  return OG_OK;
 }
 
 og_status og_read_stats(const void* ws, og_stats* stats, void* stream) {
