@@ -975,35 +975,42 @@ __global__ __launch_bounds__(kBlock) void k_pred_edge_ids(Args a, const int* pre
 
 // Backward pass of the differentiable search (reverse-topological subtree
 // sums over the shortest-path tree): grad_w[e] for the tree edge e into v
-// is the sum of grad_dist over v's subtree; non-tree edges get 0.  acc
-// (float64) and cnt (children not yet folded in) live in the workspace.
+// is the sum of grad_dist over v's subtree; non-tree edges get 0.  The
+// workspace holds acc (float64 running sums), kids (tree children, fixed
+// once counted) and pending (children not yet folded in).
 __global__ __launch_bounds__(kBlock) void k_bw_init(const float* grad_dist, int n, float* grad_w, long long m,
-                                                     double* acc, int* cnt) {
+                                                     double* acc, int* kids, int* pending) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long long v = t0; v < n; v += stride) {
     acc[v] = (double)grad_dist[v];
-    cnt[v] = 0;
+    kids[v] = 0;
+    pending[v] = 0;
   }
   for (long long e = t0; e < m; e += stride) grad_w[e] = 0.0f;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bw_count(const int* pred, const int* pred_edge, int n, int* cnt) {
+__global__ __launch_bounds__(kBlock) void k_bw_count(const int* pred, const int* pred_edge, int n, int* kids,
+                                                      int* pending) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    if (pred_edge[v] >= 0) atomicAdd(&cnt[pred[v]], 1);
+    if (pred_edge[v] >= 0) {
+      atomicAdd(&kids[pred[v]], 1);
+      atomicAdd(&pending[pred[v]], 1);
+    }
 }
 
-// Every leaf climbs towards the root, adding its subtree sum into its
-// parent; the child that folds in last (its decrement of the parent's
-// counter reaches zero) carries on from the parent, whose sum is then
-// complete.  Each addition finishes before the decrement that announces it
-// (wait on the returned value), so the last child reads the full sum.
+// Every leaf (kids == 0, never changed by this kernel) climbs towards the
+// root, adding its subtree sum into its parent; the child that folds in
+// last (its decrement of the parent's pending count reaches zero) carries
+// on from the parent, whose sum is then complete.  Each addition finishes
+// before the decrement that announces it (wait for completion), so the last
+// child reads the full sum.
 __global__ __launch_bounds__(kBlock) void k_bw_climb(const int* pred, const int* pred_edge, int n, float* grad_w,
-                                                      double* acc, int* cnt) {
+                                                      double* acc, const int* kids, int* pending) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    if (pred_edge[v] < 0 || cnt[v] != 0) continue;  // not a leaf of the tree
+    if (pred_edge[v] < 0 || kids[v] != 0) continue;  // not a leaf of the tree
     int x = (int)v;
     double val = acc[x];
     for (;;) {
@@ -1011,10 +1018,9 @@ __global__ __launch_bounds__(kBlock) void k_bw_climb(const int* pred, const int*
       if (e < 0) break;
       grad_w[e] = (float)val;
       const int p = pred[x];
-      const double before = atomicAdd(&acc[p], val);
+      (void)atomicAdd(&acc[p], val);
       wait_vm();
-      (void)before;
-      if (atomicSub(&cnt[p], 1) != 1) break;
+      if (atomicSub(&pending[p], 1) != 1) break;
       x = p;
       val = __hip_atomic_load(&acc[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1440,7 +1446,7 @@ og_status og_sssp_f32(const og_graph_f32* g, int32_t src, const og_schedule* s, 
 
 size_t og_backward_workspace_bytes(int32_t n) {
   if (n < 1) return 0;
-  const size_t b = sizeof(double) * (size_t)n + sizeof(int) * (size_t)n;
+  const size_t b = sizeof(double) * (size_t)n + 2 * sizeof(int) * (size_t)n;
   return (b + 255) & ~(size_t)255;
 }
 
@@ -1455,12 +1461,14 @@ og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const
   if (hipGetDevice(&dev) != hipSuccess || !og::device_info(dev, &di)) return OG_ERR_HIP;
   hipStream_t st = (hipStream_t)stream;
   double* acc = (double*)ws;
-  int* cnt = (int*)((char*)ws + sizeof(double) * (size_t)g->n);
+  int* kids = (int*)((char*)ws + sizeof(double) * (size_t)g->n);
+  int* pending = kids + g->n;
   const int grid = di.cus * 8;
   hipLaunchKernelGGL(og::k_bw_init, dim3(grid), dim3(og::kBlock), 0, st, grad_dist, g->n, grad_w, (long long)g->m,
-                     acc, cnt);
-  hipLaunchKernelGGL(og::k_bw_count, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, cnt);
-  hipLaunchKernelGGL(og::k_bw_climb, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, grad_w, acc, cnt);
+                     acc, kids, pending);
+  hipLaunchKernelGGL(og::k_bw_count, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, kids, pending);
+  hipLaunchKernelGGL(og::k_bw_climb, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, grad_w, acc, kids,
+                     pending);
   if (hipGetLastError() != hipSuccess) return OG_ERR_HIP;
   return OG_OK;
 }
