@@ -81,10 +81,10 @@ def summarize_rocpd(db: str, counter: str | None) -> int:
     return 0
 
 
-def _line(metric, value, unit, steps, warmup, ms_per_step, config, **extra):
+def _line(metric, value, unit, steps, warmup, ms_per_step, config, dtype="int32", higher_is_better=True, **extra):
     d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
-         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-         "dtype": "int32", "data": "synthetic", "config": config}
+         "ms_per_step": ms_per_step, "higher_is_better": higher_is_better, "scaling": "weak", "vs_baseline": None,
+         "dtype": dtype, "data": "synthetic", "config": config}
     d.update(extra)
     return json.dumps(d)
 
@@ -248,6 +248,62 @@ def workload_rgg(args) -> int:
     return 0
 
 
+def workload_diff(args) -> int:
+    """Differentiable SSSP (float32 weights U(1,1000)): loss = sum of
+    distances to 1,024 targets; forward (distances + tree) and backward
+    (dL/dw) times on the road-like 2048^2 grid and R-MAT 22."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1911_07260_amd as og
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, g, delta in (("road2048", gg.road(2048, seed=0), 4096), ("rmat22", gg.rmat(22, 16, seed=0), 64)):
+        w = gg.float_weights(g, 1.0, 1000.0, seed=3)
+        dg = og.DeviceGraph.from_host(g, dev)
+        wt = torch.from_numpy(w).to(dev).requires_grad_(True)
+        s = int(gg.pick_sources(g, 1, seed=1)[0])
+        tg = torch.from_numpy(gg.pick_sources(g, 1024, seed=3)).to(dev)
+        sched = og.Schedule(delta=delta, flags=og.OG_FLAG_TIMING)
+        times = []
+        for it in range(4):
+            wt.grad = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dist = og.shortest_path_distances(wt, dg, s, sched)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            d_t = dist[tg]
+            loss = d_t[torch.isfinite(d_t)].sum()
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if it:
+                times.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3))
+        fw, bw = np.mean([t[0] for t in times]), np.mean([t[1] for t in times])
+        parity = None
+        if not args.no_cpu:
+            import oracle
+            orc = oracle.get()
+            ref = orc.dijkstra_real(g, w, s, f32=False)
+            dn = dist.detach().cpu().numpy()
+            fin = np.isfinite(ref) & (ref > 0)
+            rel = float(np.max(np.abs(dn[fin] - ref[fin]) / ref[fin]))
+            parity = {"forward_max_rel_err_vs_f64": rel}
+        res[name] = {"n": g.n, "m": g.m, "delta": delta, "forward_ms": round(float(fw), 3),
+                     "backward_ms": round(float(bw), 3), "parity": parity}
+        print(f"[bench] diff {name}: forward {fw:.2f} ms backward {bw:.2f} ms", file=sys.stderr, flush=True)
+        del dg, wt, dist
+    r = res["road2048"]
+    print(_line("ms per forward+backward, differentiable SSSP", round(r["forward_ms"] + r["backward_ms"], 3), "ms",
+                3, 1, round(r["forward_ms"] + r["backward_ms"], 3),
+                {"workload": "float32 weights U(1,1000), loss = sum of distances to 1,024 targets; road-like "
+                             "2048^2 and R-MAT 22"}, dtype="f32", higher_is_better=False, results=res),
+          flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,7 +319,7 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-rocpd", metavar="DB")
     ap.add_argument("--counter")
-    ap.add_argument("--workload", default="road", choices=["road", "rmat", "astar", "rgg"],
+    ap.add_argument("--workload", default="road", choices=["road", "rmat", "astar", "rgg", "diff"],
                     help="road (default, the headline line) or one of the extra workloads")
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--rmat-delta", type=int, default=32)
@@ -278,7 +334,8 @@ def main() -> int:
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
             return 2
-        return {"rmat": workload_rmat, "astar": workload_astar, "rgg": workload_rgg}[args.workload](args)
+        return {"rmat": workload_rmat, "astar": workload_astar, "rgg": workload_rgg,
+                "diff": workload_diff}[args.workload](args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design is described in "
