@@ -76,6 +76,8 @@ def _bind(lib):
     lib.oracle_tree_real.argtypes = [i32, vp, vp, vp, i32, vp, ctypes.c_int, vp, vp]
     lib.oracle_subtree_grad.restype = ctypes.c_int
     lib.oracle_subtree_grad.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+    lib.oracle_kcore.restype = ctypes.c_int
+    lib.oracle_kcore.argtypes = [i32, vp, vp, vp]
     return lib
 
 
@@ -196,6 +198,14 @@ class Oracle:
                                         up.ctypes.data, gw.ctypes.data) != 0:
             raise MemoryError("oracle_subtree_grad")
         return gw
+
+    def kcore(self, g) -> np.ndarray:
+        """Coreness of every vertex (int32) by minimum-degree peeling."""
+        rp, col, _ = self._csr(g)
+        core = np.empty(g.n, dtype=np.int32)
+        if self.lib.oracle_kcore(g.n, rp.ctypes.data, col.ctypes.data, core.ctypes.data) != 0:
+            raise ValueError("oracle_kcore: bad arguments")
+        return core
 
     def check(self, g, src: int, dist32: np.ndarray, pred: np.ndarray | None = None) -> int:
         """Bitmask of violated shortest-path certificate invariants."""

@@ -30,6 +30,10 @@
  *   - A*: s, d and a per-vertex estimate h; with an admissible h the result
  *     is again the s-d shortest distance (textbook A* with re-opening).
  *
+ *   - Lazy bucket update (Figure "lazy bucket update"): the same
+ *     distances; only the bucket bookkeeping differs.
+ *   - k-core (section 6.1): coreness of every vertex, by peeling.
+ *
  * Predecessors are not discussed in the paper.  The reading used here is
  * the canonical one: pred[v] = smallest u with an edge (u,v) such that
  * dist[u] is finite and dist[u] + w(u,v) == dist[v]; pred[s] = s; -1 when
@@ -529,5 +533,51 @@ int oracle_subtree_grad(int32_t n, int64_t m, const double* dist, const int32_t*
   }
   free(order);
   free(acc);
+  return 0;
+}
+
+/* ---------------- k-core decomposition (section 6.1, k-core) ----------------
+ * coreness[v] = the largest k such that v belongs to the k-core, the
+ * maximal subgraph in which every vertex keeps at least k neighbours.  The
+ * paper computes it by peeling (Matula and Beck): repeatedly remove a vertex
+ * of minimum remaining degree; the coreness of the removed vertex is the
+ * largest minimum degree seen so far.  That is what this function does,
+ * with a binary heap keyed by remaining degree (stale heap entries are
+ * skipped).  The graph is given by symmetric rows: the degree of v is its
+ * row length, and removing v lowers the degree of every vertex in its row.
+ * Returns 0, or -1 on allocation failure / bad arguments. */
+int oracle_kcore(int32_t n, const int64_t* row_ptr, const int32_t* col, int32_t* core) {
+  if (n <= 0) return -1;
+  int64_t* deg = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  unsigned char* gone = (unsigned char*)calloc((size_t)n, 1);
+  heap_t h;
+  if (!deg || !gone || !heap_init(&h, n)) { free(deg); free(gone); return -1; }
+  for (int32_t v = 0; v < n; ++v) {
+    deg[v] = row_ptr[v + 1] - row_ptr[v];
+    if (!heap_push(&h, deg[v], v)) { free(deg); free(gone); heap_free(&h); return -1; }
+  }
+  int64_t level = 0;
+  while (h.size > 0) {
+    int64_t d;
+    int32_t v;
+    heap_pop(&h, &d, &v);
+    if (gone[v] || d != deg[v]) continue; /* removed, or superseded by a lower degree */
+#if ORACLE_MUTATION == 5
+    level = d; /* planted: the level may go down */
+#else
+    if (d > level) level = d;
+#endif
+    core[v] = (int32_t)level;
+    gone[v] = 1;
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      int32_t u = col[e];
+      if (gone[u]) continue;
+      deg[u] -= 1;
+      if (!heap_push(&h, deg[u], u)) { free(deg); free(gone); heap_free(&h); return -1; }
+    }
+  }
+  free(deg);
+  free(gone);
+  heap_free(&h);
   return 0;
 }
