@@ -71,6 +71,13 @@ typedef int32_t og_status;
 /* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
 #define OG_EAGER_NO_FUSION 0
 #define OG_EAGER_WITH_FUSION 1
+#define OG_LAZY_UPDATE 2 /* section 3.1: a round only records which vertices
+                            changed (each once, by a flag); after a device-wide
+                            barrier each of them is filed once into the bucket
+                            of its final priority.  Two barriers per round, no
+                            fusion.  For og_kcore the recorded change is a
+                            count of lost neighbours (constant-sum reduction,
+                            section 5.1).                                     */
 
 /* Engines. */
 #define OG_ENGINE_PERSISTENT 0 /* one cooperative launch, device-wide barrier
@@ -90,10 +97,11 @@ typedef struct og_graph {
  * og_default_schedule() fills them in explicitly. */
 typedef struct og_schedule {
   int32_t delta;            /* Delta >= 1: bucket = floor(priority/Delta)     */
-  int32_t update;           /* OG_EAGER_WITH_FUSION (default) or ..._NO_FUSION */
+  int32_t update;           /* OG_EAGER_WITH_FUSION (default), ..._NO_FUSION
+                               or OG_LAZY_UPDATE                              */
   int32_t fusion_threshold; /* a workgroup keeps processing its local current
                                bucket while it holds fewer entries than this
-                               (0 = 1024; capped at the LDS queue, 2048)      */
+                               (0 = 1024; capped at the LDS queue, 1024)      */
   int32_t window_buckets;   /* buckets materialised at once, 2..64 (0 = 16);
                                later ones wait in an overflow ("far") queue   */
   int32_t engine;           /* OG_ENGINE_PERSISTENT (default) / _HOST_ROUNDS  */
@@ -101,14 +109,15 @@ typedef struct og_schedule {
                                rounds (0 = unlimited)                         */
   int32_t workgroups;       /* workgroups to launch (0 = all co-resident)     */
   uint32_t flags;           /* OG_FLAG_*                                      */
-  int64_t queue_capacity;   /* entries per global queue (0 = n + m/8)         */
+  int64_t queue_capacity;   /* entries per global queue (0 = n + m/8; og_kcore:
+                               2n + m/8)                                      */
 } og_schedule;
 
 /* Per-call counters (host struct). */
 typedef struct og_stats {
   og_status status;
   int32_t workgroups;       /* workgroups launched                            */
-  int64_t rounds;           /* global synchronisations (barriers or launches) */
+  int64_t rounds;           /* rounds (bucket decisions)                      */
   int64_t buckets;          /* distinct buckets processed                     */
   int64_t relaxations;      /* edges examined                                 */
   int64_t improvements;     /* successful atomic minimum updates              */
@@ -126,6 +135,8 @@ typedef struct og_stats {
   int64_t chain;            /* sum over rounds of the most batches any one
                                workgroup processed in that round (the engine's
                                critical path in batch steps)                  */
+  int64_t barriers;         /* device-wide synchronisations: one per round, two
+                               with OG_LAZY_UPDATE                            */
 } og_stats;
 
 /* Library version, (major << 16) | minor. */
@@ -239,6 +250,26 @@ og_status og_sssp_f32(const og_graph_f32* g, int32_t src, const og_schedule* s, 
 size_t og_backward_workspace_bytes(int32_t n);
 og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const int32_t* pred_edge,
                                const float* grad_dist, float* grad_w, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- k-core decomposition (section 6.1, k-core) ------------------------
+ * core[v] = the coreness of v: the largest k such that v lies in a subgraph
+ * whose every vertex keeps at least k neighbours.  The graph must be
+ * undirected (both directions stored); the degree of v is its row length
+ * and w may be NULL (weights are not read).  Vertices are peeled in
+ * increasing order of remaining degree, one bucket per degree value (Delta
+ * is not used: the order is strict, section 2).  core is also the priority
+ * vector during the call.  update:
+ *   OG_LAZY_UPDATE (recommended): a round counts, per neighbour, how many of
+ *     its neighbours were peeled (one atomic increment each) and then lowers
+ *     each counted neighbour's degree once by that count, clamped at the
+ *     current level (the constant-sum reduction of section 5.1);
+ *   OG_EAGER_NO_FUSION / OG_EAGER_WITH_FUSION: every peeled edge lowers the
+ *     neighbour's degree by one at once (compare-and-swap, clamped at the
+ *     current level) and files it in its new bucket.
+ * Workspace: og_workspace_bytes_kcore(). */
+size_t og_workspace_bytes_kcore(const og_graph* g, const og_schedule* s);
+og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void* ws, size_t ws_bytes,
+                   og_stats* stats, void* stream);
 
 /* Reads the status and counters of the last call made with workspace ws
  * (device) into *stats (host); used after an OG_FLAG_ASYNC call once the

@@ -8,9 +8,10 @@ kernels.  Functions mirror the C ABI:
     wbfs(graph, src, schedule)        og_wbfs   (Delta forced to 1)
     ppsp(graph, src, dst, schedule)   og_ppsp
     astar(graph, src, dst, h, sched)  og_astar
+    kcore(graph, schedule)            og_kcore  (coreness of every vertex)
 
-Each returns ``(dist, pred, stats)`` with int32 device tensors (pred is None
-when not requested) and a dict of counters.
+Each shortest-path call returns ``(dist, pred, stats)`` with int32 device
+tensors (pred is None when not requested) and a dict of counters.
 """
 from __future__ import annotations
 
@@ -20,16 +21,16 @@ from dataclasses import dataclass, field, fields
 import torch
 
 from . import _lib
-from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_HOST_ROUNDS, OG_ENGINE_PERSISTENT,
-                   OG_ERR_HIP, OG_ERR_INVALID_ARG, OG_ERR_NEGATIVE_WEIGHT, OG_ERR_OVERFLOW, OG_ERR_ROUND_LIMIT,
-                   OG_ERR_WORKSPACE, OG_FLAG_ASYNC, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_OK, OgError, OgGraph, OgSchedule,
+from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_HOST_ROUNDS, OG_ENGINE_PERSISTENT, OG_ERR_HIP,
+                   OG_ERR_INVALID_ARG, OG_ERR_NEGATIVE_WEIGHT, OG_ERR_OVERFLOW, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE,
+                   OG_FLAG_ASYNC, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, OG_OK, OgError, OgGraph, OgSchedule,
                    OgStats)
 
 INF = 2**31 - 1
 
 __all__ = [
     "DeviceGraph", "Schedule", "Workspace", "sssp", "wbfs", "ppsp", "astar", "sssp_batch", "ppsp_batch",
-    "astar_batch", "sssp_multi", "workspace_bytes", "status_string", "version", "INF", "OgError",
+    "astar_batch", "sssp_multi", "kcore", "workspace_bytes", "status_string", "version", "INF", "OgError",
 ]
 
 
@@ -57,19 +58,21 @@ class Schedule:
 class DeviceGraph:
     """Directed CSR graph resident on a device (int64 row_ptr, int32 col, w)."""
 
-    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, w: torch.Tensor):
-        assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32 and w.dtype == torch.int32
-        assert row_ptr.is_contiguous() and col.is_contiguous() and w.is_contiguous()
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, w: torch.Tensor | None):
+        assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32
+        assert row_ptr.is_contiguous() and col.is_contiguous()
+        assert w is None or (w.dtype == torch.int32 and w.is_contiguous())
         self.row_ptr, self.col, self.w = row_ptr, col, w
         self.n = row_ptr.numel() - 1
         self.m = col.numel()
 
     @classmethod
-    def from_host(cls, g, device="cuda"):
-        """From any object with numpy row_ptr / col / w (e.g. graphgen.Graph)."""
+    def from_host(cls, g, device="cuda", weights: bool = True):
+        """From any object with numpy row_ptr / col / w (e.g. graphgen.Graph);
+        weights=False leaves w out (og_kcore does not read it)."""
         rp = torch.from_numpy(g.row_ptr).to(device=device, dtype=torch.int64).contiguous()
         col = torch.from_numpy(g.col).to(device=device, dtype=torch.int32).contiguous()
-        w = torch.from_numpy(g.w).to(device=device, dtype=torch.int32).contiguous()
+        w = torch.from_numpy(g.w).to(device=device, dtype=torch.int32).contiguous() if weights else None
         return cls(rp, col, w)
 
     @property
@@ -79,7 +82,7 @@ class DeviceGraph:
     def to_c(self) -> OgGraph:
         return OgGraph(self.n, self.m, self.row_ptr.data_ptr(),
                        self.col.data_ptr() if self.m else None,
-                       self.w.data_ptr() if self.m else None)
+                       self.w.data_ptr() if (self.m and self.w is not None) else None)
 
 
 def version() -> int:
@@ -226,6 +229,37 @@ def sssp_multi(graph: DeviceGraph, srcs, schedule: Schedule | None = None, pred:
     s_ = _host_ids(srcs)
     return _call("og_sssp_multi", graph, [ctypes.c_void_p(s_.ctypes.data), len(s_)], schedule, pred, ws, stream,
                  multi=len(s_), **kw)
+
+
+def kcore(graph: DeviceGraph, schedule: Schedule | None = None, ws: Workspace | None = None, stream=None,
+          out: torch.Tensor | None = None, check: bool = True):
+    """k-core decomposition (og_kcore): (coreness int32 [n], stats).  The
+    graph must store both directions of every edge; weights are not read.
+    schedule.update: OG_LAZY_UPDATE (histogram reduction) or an eager mode;
+    delta is ignored."""
+    lib = _lib.load()
+    schedule = schedule or Schedule(update=OG_LAZY_UPDATE)
+    g = graph.to_c()
+    s = schedule.to_c()
+    nbytes = int(lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s)))
+    if nbytes == 0:
+        raise OgError(OG_ERR_INVALID_ARG, "og_workspace_bytes_kcore", lib)
+    if ws is None:
+        ws = _default_ws.setdefault(str(graph.device), Workspace(graph.device))
+    buf = ws.get(nbytes)
+    core = out if out is not None else torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+    assert core.numel() == graph.n and core.dtype == torch.int32 and core.is_contiguous()
+    st = OgStats()
+    if stream is None:
+        stream = torch.cuda.current_stream(graph.device)
+    status = lib.og_kcore(ctypes.byref(g), ctypes.byref(s), ctypes.c_void_p(core.data_ptr()),
+                          ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(buf.numel()), ctypes.byref(st),
+                          ctypes.c_void_p(stream.cuda_stream))
+    stats = st.as_dict()
+    stats["status"] = int(status)
+    if check and status != OG_OK:
+        raise OgError(status, "og_kcore", lib)
+    return core, stats
 
 
 from .diff import ShortestPathDistances, shortest_path_distances, sssp_backward_f32, sssp_f32  # noqa: E402

@@ -26,6 +26,7 @@ OG_FLAG_TIMING = 4
 
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1
+OG_LAZY_UPDATE = 2
 
 OG_ENGINE_PERSISTENT = 0
 OG_ENGINE_HOST_ROUNDS = 1
@@ -84,6 +85,7 @@ class OgStats(ctypes.Structure):
         ("pred_ms", ctypes.c_double),
         ("batches", ctypes.c_int64),
         ("chain", ctypes.c_int64),
+        ("barriers", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -151,6 +153,10 @@ def load():
     lib.og_backward_workspace_bytes.argtypes = [i32]
     lib.og_sssp_backward_f32.restype = i32
     lib.og_sssp_backward_f32.argtypes = [P(OgGraphF32), vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.og_workspace_bytes_kcore.restype = ctypes.c_size_t
+    lib.og_workspace_bytes_kcore.argtypes = [P(OgGraph), P(OgSchedule)]
+    lib.og_kcore.restype = i32
+    lib.og_kcore.argtypes = [P(OgGraph), P(OgSchedule), vp, vp, ctypes.c_size_t, P(OgStats), vp]
     lib.og_read_stats.restype = i32
     lib.og_read_stats.argtypes = [vp, P(OgStats), vp]
     _lib = lib

@@ -64,6 +64,7 @@ constexpr int kMaxQueries = 1024;
 constexpr size_t kCtlBytes = 65536;
 constexpr unsigned kNoBucket = 0xffffffffu;
 constexpr int kInf = INT_MAX;
+constexpr int kPeeled = INT_MAX;  // k-core mark of a peeled vertex (above every generation)
 
 enum : int { kInWin = 0, kInSpill = 1, kInFar = 2 };
 enum : int {
@@ -90,6 +91,8 @@ struct alignas(128) Control {
   unsigned win_hi;     // buckets >= win_hi go to the far list
   unsigned round;
   unsigned buckets;
+  unsigned epoch;    // device-wide barriers completed
+  unsigned far_gen;  // generation of the pending far list (k-core filing)
 };
 
 // Device-side control block at the start of the workspace.
@@ -105,6 +108,7 @@ struct Ctl {
   Word far_tail[2];
   Word far_min[2];
   Word round_max_batches;  // most batches one workgroup ran in the current round
+  Word buf_tail;           // lazy update: entries in the change buffer
   Word64 need;
   Word64 st[kStCount];
 };
@@ -134,6 +138,12 @@ struct Args {
   int2* win;
   int2* spill;
   int2* far;
+  int lazy;       // lazy bucket update: record changes, file them after a barrier
+  int* aux;       // [n] lazy: change flag (SSSP) or lost-neighbour count (k-core)
+  int* buf;       // [buf_cap] lazy: vertices changed this round, each once
+  unsigned buf_cap;
+  int* mark;      // [n] k-core: kPeeled once peeled, else the newest far-list
+                  // generation the vertex was filed in
 };
 
 struct Counters {
@@ -156,7 +166,7 @@ struct Smem {
   int exhausted;
   int last;
   // snapshot of the control block for this round
-  unsigned cur, in_count, win_hi, round;
+  unsigned cur, in_count, win_hi, round, epoch, far_stamp;
   int in_kind, in_index, done, spill_out, far_out;
 };
 
@@ -259,6 +269,10 @@ struct FloatW {
   }
 };
 
+// k-core: the priority of a vertex is its remaining degree (the "dist"
+// array is the priority vector), one bucket per value; no weights.
+struct CoreW : IntW {};
+
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
   int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
   return base + (size_t)index * a.cap;
@@ -335,6 +349,23 @@ __device__ void wave_push_global(const Args& a, const Smem& s, Counters& c, bool
         tgt = K + 1;
       }
     }
+  }
+}
+
+// Lazy update: appends the lanes' vertices to the change buffer (one atomic
+// per wavefront).  Each vertex is appended at most once per round (the
+// caller holds its flag), so the buffer never exceeds n entries.
+__device__ void wave_append_buf(const Args& a, bool has, int v) {
+  const unsigned long long m = __ballot(has);
+  if (m == 0) return;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(&a.ctl->buf_tail.v, (unsigned)__popcll(m));
+  base = __shfl(base, leader);
+  if (has) {
+    const unsigned pos = base + (unsigned)__popcll(m & lanemask_lt());
+    if (pos < a.buf_cap) st_dev(reinterpret_cast<unsigned*>(a.buf) + pos, (unsigned)v);
+    else set_status(a.ctl, OG_ERR_WORKSPACE);
   }
 }
 
@@ -475,7 +506,155 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
         }
       }
     }
-    route_push(a, s, c, has, u, (int)nd, b, r0, rdeg);
+    if (a.lazy) {
+      // record the change once per round; its bucket is filed after the round
+      const bool first = has && atomicExch(&a.aux[u], 1) == 0;
+      wave_append_buf(a, first, u);
+    } else {
+      route_push(a, s, c, has, u, (int)nd, b, r0, rdeg);
+    }
+  }
+}
+
+// k-core filing of vertex u at priority p (> the current level, or equal to
+// it for the current bucket).  A priority at or beyond the window goes to
+// the far list only if u is not already filed in that list (the far list is
+// re-read by current priority when it is redistributed), so it holds each
+// vertex at most once; far_min still records p.  A peeled vertex (mark
+// kPeeled, above every generation) is never filed there again.
+__device__ void route_core(const Args& a, Smem& s, Counters& c, bool has, int u, int p, int r0, int deg) {
+  if (has && (unsigned)p >= s.win_hi) {
+    atomicMin(&a.ctl->far_min[s.far_out].v, (unsigned)p);
+    if (atomicMax(&a.mark[u], (int)s.far_stamp) >= (int)s.far_stamp) has = false;
+  }
+  route_push(a, s, c, has, u, p, (unsigned)p, r0, deg);
+}
+
+// k-core frontier batch (section 6.1 peeling at level k = current bucket).
+// An entry (v, p) is live when v is not yet peeled and its current degree
+// equals k; the peel mark (kPeeled) makes each vertex peel once even if it
+// was filed more than once.  An entry whose vertex now has a larger
+// degree (a far-list entry being redistributed) is filed by that degree.
+// Every edge of a peeled vertex lowers the neighbour's degree if it is above
+// k: lazily (count it; the change is applied once after the round) or
+// eagerly (compare-and-swap one lower, never below k, and file it).
+__device__ void process_batch_core(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds) {
+  const int tid = threadIdx.x;
+  const unsigned cur = s.cur;
+  const int v = ent.x;
+  int deg = 0, start = 0, now = 0;
+  bool refile = false;
+  if (v >= 0) {
+    now = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + v);
+    const int mk = (int)ld_dev(reinterpret_cast<const unsigned*>(a.mark) + v);
+    if (mk != kPeeled) {
+      if ((unsigned)now == cur) {
+        if (atomicExch(&a.mark[v], kPeeled) != kPeeled) {  // peel v at level cur
+          if (from_lds) {
+            start = ent.z;
+            deg = ent.w;
+          } else {
+            const long long r0 = a.row_ptr[v];
+            start = (int)r0;
+            deg = (int)(a.row_ptr[v + 1] - r0);
+          }
+        }
+      } else if ((unsigned)now > cur) {
+        refile = true;
+      }
+    }
+  }
+  route_core(a, s, c, refile, v, now, 0, 0);
+  int total;
+  const int off = block_excl_scan(deg, s, &total);
+  s.boff[tid] = off;
+  s.bstart[tid] = start;
+  __syncthreads();
+  const int nb = s.nb;
+  for (int base = 0; base < total; base += kBlock) {
+    const int e = base + tid;
+    bool has = false;
+    int u = 0, nd = 0, r0 = 0, rdeg = 0;
+    if (e < total) {
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.boff[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      u = a.col[s.bstart[lo] + (e - s.boff[lo])];
+      c.relax++;
+      int du = a.dist[u];  // a past value: never below the current one
+      if (du > (int)cur) {
+        if (a.lazy) {
+          has = atomicAdd(&a.aux[u], 1) == 0;  // first count of u this round
+        } else {
+          while (du > (int)cur) {
+            const int old = atomicCAS(&a.dist[u], du, du - 1);
+            if (old == du) {
+              has = true;
+              nd = du - 1;
+              break;
+            }
+            du = old;
+          }
+          if (has) {
+            c.improve++;
+            if (a.fused && (unsigned)nd == cur) {
+              const long long q0 = a.row_ptr[u];
+              r0 = (int)q0;
+              rdeg = (int)(a.row_ptr[u + 1] - q0);
+            }
+          }
+        }
+      }
+    }
+    if (a.lazy) wave_append_buf(a, has, u);
+    else route_core(a, s, c, has, u, nd, r0, rdeg);
+  }
+}
+
+// Second phase of a lazy round (section 3.1, reduce the buffered updates and
+// file them in bulk): every vertex recorded in the change buffer is filed
+// once, by its final priority.  SSSP: the final distance's bucket.  k-core
+// (constant-sum reduction, section 5.1): the degree drops by the number of
+// peeled neighbours counted in the round, clamped at the current level.
+template <class W>
+__device__ void run_flush(const Args& a, Smem& s, Counters& c) {
+  const unsigned cnt0 = ld_dev(&a.ctl->buf_tail.v);
+  const unsigned cnt = cnt0 < a.buf_cap ? cnt0 : a.buf_cap;
+  const unsigned cur = s.cur;
+  for (unsigned base = blockIdx.x * (unsigned)kBlock; base < cnt; base += (unsigned)a.nwg * kBlock) {
+    const unsigned i = base + threadIdx.x;
+    bool has = false;
+    int u = 0, d = 0;
+    unsigned b = 0;
+    if (i < cnt) {
+      u = (int)ld_dev(reinterpret_cast<const unsigned*>(a.buf) + i);
+      if constexpr (std::is_same<W, CoreW>::value) {
+        const int k = atomicExch(&a.aux[u], 0);
+        const int now = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + u);
+        if (now > (int)cur) {
+          d = now - k > (int)cur ? now - k : (int)cur;
+          st_dev(reinterpret_cast<unsigned*>(a.dist) + u, (unsigned)d);
+          has = true;
+          c.improve++;
+        }
+      } else {
+        st_dev(reinterpret_cast<unsigned*>(a.aux) + u, 0u);
+        d = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + u);
+        b = W::bucket(a, W::key(a, u, d));
+        if (b < cur) b = cur;
+        has = true;
+      }
+    }
+    if constexpr (std::is_same<W, CoreW>::value) {
+      route_core(a, s, c, has, u, d, 0, 0);
+    } else {
+      int tgt = 0;
+      if (has) tgt = b == cur ? a.K : (b < s.win_hi ? (int)(b & (unsigned)(a.K - 1)) : a.K + 1);
+      wave_push_global(a, s, c, has, tgt, u, d, b);
+    }
   }
 }
 
@@ -576,7 +755,8 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
         ent = make_int4(e.x, e.y, 0, 0);
       }
     }
-    process_batch<W>(a, s, c, ent, mode == 1);
+    if constexpr (std::is_same<W, CoreW>::value) process_batch_core(a, s, c, ent, mode == 1);
+    else process_batch<W>(a, s, c, ent, mode == 1);
     c.batches++;
     c.round_batches++;
   }
@@ -642,6 +822,9 @@ __device__ void decide(const Args& a) {
     st_dev(&c->far_min[in_index].v, kNoBucket);
   }
   st_dev(&c->in_head.v, 0);
+  st_dev(&c->buf_tail.v, 0);
+  // a consumed far list hands its role to the other one (next generation)
+  st_dev(&c->c.far_gen, ld_dev(&c->c.far_gen) + (in_kind == kInFar ? 1u : 0u));
   {
     const unsigned rm = __hip_atomic_exchange(&c->round_max_batches.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     atomicAdd(&c->st[kStChain].v, (unsigned long long)rm);
@@ -721,18 +904,20 @@ __device__ void load_control(const Args& a, Smem& s) {
   s.round = ld_dev(&c->c.round);
   const int far_in = (int)ld_dev(&c->c.far_in);
   s.far_out = s.in_kind == kInFar ? 1 - far_in : far_in;
+  s.far_stamp = ld_dev(&c->c.far_gen) + (s.in_kind == kInFar ? 1u : 0u);
+  s.epoch = ld_dev(&c->c.epoch);
   s.done = ld_dev(&c->c.done) || ld_dev(&c->status.v) != 0;
 }
 
-// End-of-round synchronisation across the grid.  Every wavefront waits for
-// its own stores and atomics to complete; thread 0 of each workgroup then
-// arrives on its group's counter (kGroup workgroups per counter, each on its
-// own cache line), the last of a group arrives on the root counter, and the
-// last workgroup overall runs the bucket decision with wave 0 and publishes
-// the next round number on kFlags release flags.  With wait_others (the
-// persistent engine) every other workgroup spins on one of those flags;
-// the host-driven engine ends the kernel instead.
-__device__ void round_barrier(const Args& a, Smem& s, Counters& c, bool wait_others) {
+// Device-wide synchronisation.  Every wavefront waits for its own stores
+// and atomics to complete; thread 0 of each workgroup then arrives on its
+// group's counter (kGroup workgroups per counter, each on its own cache
+// line), the last of a group arrives on the root counter, and the last
+// workgroup overall (with decide_next: after taking the bucket decision with
+// wave 0) publishes the new barrier count on kFlags release flags.  With
+// wait_others (the persistent engine) every other workgroup spins on one of
+// those flags; the host-driven engine ends the kernel instead.
+__device__ void round_barrier(const Args& a, Smem& s, Counters& c, bool wait_others, bool decide_next) {
   Ctl* ctl = a.ctl;
   if (threadIdx.x == 0) atomicMax(&ctl->round_max_batches.v, c.round_batches);
   c.round_batches = 0;
@@ -755,18 +940,20 @@ __device__ void round_barrier(const Args& a, Smem& s, Counters& c, bool wait_oth
     s.last = last;
   }
   __syncthreads();
+  const unsigned next = s.epoch + 1;
   if (s.last) {
     if (threadIdx.x < kWave) {
-      decide(a);
+      if (decide_next) decide(a);
+      if (threadIdx.x == 0) st_dev(&ctl->c.epoch, next);
       wait_vm();
-      st_dev(&ctl->flag[threadIdx.x].v, s.round + 1);
+      st_dev(&ctl->flag[threadIdx.x].v, next);
     }
   } else if (wait_others && threadIdx.x == 0) {
-    const unsigned want = s.round + 1;
     const unsigned* f = &ctl->flag[blockIdx.x % kFlags].v;
-    while (ld_dev(f) < want) __builtin_amdgcn_s_sleep(2);
+    while (ld_dev(f) < next) __builtin_amdgcn_s_sleep(2);
   }
   __syncthreads();
+  if (threadIdx.x == 0) s.epoch = next;
 }
 
 __device__ void flush_counters(const Args& a, const Counters& c) {
@@ -799,7 +986,10 @@ __global__ void k_put_table(int* table, TableChunk tc) {
 
 __global__ __launch_bounds__(kBlock) void k_init(Args a, int inf_bits) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) a.dist[v] = inf_bits;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    a.dist[v] = inf_bits;
+    if (a.aux) a.aux[v] = 0;
+  }
   // zero the control block (grid-stride over its words)
   unsigned* words = reinterpret_cast<unsigned*>(a.ctl);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (long long)(sizeof(Ctl) / 4); i += stride)
@@ -819,6 +1009,34 @@ __global__ __launch_bounds__(kBlock) void k_init_sources(Args a) {
     st_entry(a.far, (size_t)i, s, 0);
     atomicMin(&c->far_min[0].v, W::bucket(a, W::key(a, s, 0)));
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_ctl(Ctl* ctl) {
+  unsigned* words = reinterpret_cast<unsigned*>(ctl);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (long long)(sizeof(Ctl) / 4);
+       i += (long long)gridDim.x * blockDim.x)
+    words[i] = 0;
+}
+
+// k-core: the priority vector starts at every vertex's degree and every
+// vertex is filed in far list 0 (generation 0) with that priority; the
+// first round is a far round at the smallest degree.
+__global__ __launch_bounds__(kBlock) void k_init_core(Args a) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  unsigned lo = kNoBucket;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < a.n; v += stride) {
+    const int d = (int)(a.row_ptr[v + 1] - a.row_ptr[v]);
+    a.dist[v] = d;
+    a.mark[v] = 0;
+    if (a.aux) a.aux[v] = 0;
+    st_entry(a.far, (size_t)v, (int)v, d);
+    lo = (unsigned)d < lo ? (unsigned)d : lo;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned y = __shfl_xor(lo, o);
+    lo = y < lo ? y : lo;
+  }
+  if (lane_id() == 0 && lo != kNoBucket) atomicMin(&a.ctl->far_min[0].v, lo);
 }
 
 __global__ void k_init_ctl(Args a) {
@@ -849,7 +1067,8 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int* w, long long m, 
 }
 
 // Persistent engine: one cooperative launch; rounds separated by a
-// device-wide barrier whose last arriver takes the bucket decision.
+// device-wide barrier whose last arriver takes the bucket decision.  A lazy
+// round has a second barrier between recording the changes and filing them.
 template <class W>
 __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   __shared__ Smem s;
@@ -858,24 +1077,34 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   __syncthreads();
   while (!s.done) {
     run_round<W>(a, s, c);
-    round_barrier(a, s, c, true);
+    if (a.lazy) {
+      round_barrier(a, s, c, true, false);
+      run_flush<W>(a, s, c);
+    }
+    round_barrier(a, s, c, true, true);
     if (threadIdx.x == 0) load_control(a, s);
     __syncthreads();
   }
   flush_counters(a, c);
 }
 
-// Host-driven engine: one launch per round; the last workgroup to finish
-// takes the bucket decision for the next launch.
+// Host-driven engine: one launch per round (two for a lazy round: phase 0
+// records, phase 1 files); the last workgroup to finish the round takes the
+// bucket decision for the next launch.
 template <class W>
-__global__ __launch_bounds__(kBlock) void k_round(Args a) {
+__global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
   __shared__ Smem s;
   Counters c;
   if (threadIdx.x == 0) load_control(a, s);
   __syncthreads();
   if (s.done) return;
-  run_round<W>(a, s, c);
-  round_barrier(a, s, c, false);
+  if (phase == 0) {
+    run_round<W>(a, s, c);
+    round_barrier(a, s, c, false, !a.lazy);
+  } else {
+    run_flush<W>(a, s, c);
+    round_barrier(a, s, c, false, true);
+  }
   flush_counters(a, c);
 }
 
@@ -1033,6 +1262,7 @@ struct DeviceInfo {
   int cus = 0;
   int occ_int = 0;    // co-resident k_persistent<IntW> workgroups per CU
   int occ_float = 0;  // co-resident k_persistent<FloatW> workgroups per CU
+  int occ_core = 0;   // co-resident k_persistent<CoreW> workgroups per CU
   int coop = 0;
   bool valid = false;
 };
@@ -1050,6 +1280,8 @@ bool device_info(int dev, DeviceInfo* out) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_int, k_persistent<IntW>, kBlock, 0) != hipSuccess)
       return false;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_float, k_persistent<FloatW>, kBlock, 0) != hipSuccess)
+      return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_core, k_persistent<CoreW>, kBlock, 0) != hipSuccess)
       return false;
     di.valid = true;
   }
@@ -1079,7 +1311,7 @@ thread_local Timers t_timers;
 
 og_schedule resolved(const og_schedule* s) {
   og_schedule r = *s;
-  if (r.update != OG_EAGER_NO_FUSION) r.update = OG_EAGER_WITH_FUSION;
+  if (r.update != OG_EAGER_NO_FUSION && r.update != OG_LAZY_UPDATE) r.update = OG_EAGER_WITH_FUSION;
   if (r.fusion_threshold <= 0) r.fusion_threshold = kDefaultThreshold;
   if (r.fusion_threshold > kLq) r.fusion_threshold = kLq;
   if (r.window_buckets <= 0) r.window_buckets = kDefaultK;
@@ -1087,16 +1319,18 @@ og_schedule resolved(const og_schedule* s) {
   return r;
 }
 
-// A call's shape: reps copies of the graph, nsrc sources, targets or not.
+// A call's shape: reps copies of the graph, nsrc sources, targets or not;
+// core: a k-core decomposition (every vertex starts filed, no sources).
 struct Shape {
   int reps;
   int nsrc;
   bool targets;
+  bool core = false;
 };
 
 long long queue_cap(const og_graph* g, const og_schedule* r, const Shape& sh) {
-  long long cap = r->queue_capacity > 0 ? r->queue_capacity
-                                        : (long long)sh.reps * ((long long)g->n + g->m / 8) + sh.nsrc;
+  const long long per = sh.core ? 2LL * g->n + g->m / 8 : (long long)g->n + g->m / 8;
+  long long cap = r->queue_capacity > 0 ? r->queue_capacity : (long long)sh.reps * per + (sh.core ? 0 : sh.nsrc);
   if (cap < 1024) cap = 1024;
   if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
   if (cap < sh.nsrc) cap = sh.nsrc;  // the sources start in a far list
@@ -1104,21 +1338,31 @@ long long queue_cap(const og_graph* g, const og_schedule* r, const Shape& sh) {
 }
 
 size_t table_bytes(const Shape& sh) {
+  if (sh.core) return 0;
   const size_t b = sizeof(int) * ((size_t)sh.nsrc + (sh.targets ? (size_t)sh.reps : 0));
   return (b + 255) & ~(size_t)255;
 }
+
+// Per-vertex int arrays after the queues: lazy change flags / counts and
+// the change buffer (lazy), peel marks (k-core); each 256-byte aligned.
+size_t vec_bytes(long long n) { return ((size_t)n * sizeof(int) + 255) & ~(size_t)255; }
 
 size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   const long long cap = queue_cap(g, r, sh);
   const size_t lists = (size_t)r->window_buckets + 4;  // K window slots, 2 spill, 2 far
   size_t b = kCtlBytes + table_bytes(sh) + lists * (size_t)cap * sizeof(int2);
-  return (b + 255) & ~(size_t)255;
+  b = (b + 255) & ~(size_t)255;
+  const long long nv = (long long)sh.reps * g->n;
+  if (r->update == OG_LAZY_UPDATE) b += 2 * vec_bytes(nv);
+  if (sh.core) b += vec_bytes(nv);
+  return b;
 }
 
 bool schedule_ok(const og_schedule* s) {
   if (!s) return false;
   if (s->delta < 1) return false;
-  if (s->update != OG_EAGER_NO_FUSION && s->update != OG_EAGER_WITH_FUSION) return false;
+  if (s->update != OG_EAGER_NO_FUSION && s->update != OG_EAGER_WITH_FUSION && s->update != OG_LAZY_UPDATE)
+    return false;
   if (s->fusion_threshold < 0 || s->window_buckets < 0 || s->window_buckets > kKmax) return false;
   if (s->window_buckets == 1) return false;
   if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS) return false;
@@ -1127,9 +1371,9 @@ bool schedule_ok(const og_schedule* s) {
   return true;
 }
 
-bool graph_ok(const og_graph* g) {
+bool graph_ok(const og_graph* g, bool weighted = true) {
   if (!g || g->n < 1 || g->m < 0 || g->m > 0x7fffffffLL || !g->row_ptr) return false;
-  if (g->m > 0 && (!g->col || !g->w)) return false;
+  if (g->m > 0 && (!g->col || (weighted && !g->w))) return false;
   return true;
 }
 
@@ -1154,6 +1398,7 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   st->queue_needed = (int64_t)h.need.v;
   st->batches = (int64_t)h.st[kStBatches].v;
   st->chain = (int64_t)h.st[kStChain].v;
+  st->barriers = (int64_t)h.c.epoch;
 }
 
 // Common driver.  vsrcs: nsrc virtual source ids; vtgts: reps virtual
@@ -1176,7 +1421,9 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   if (!device_info(dev, &di)) return fail(OG_ERR_HIP);
   const bool persistent = r.engine == OG_ENGINE_PERSISTENT;
   if (persistent && !di.coop) return fail(OG_ERR_HIP);
-  const int occ = std::is_same<W, FloatW>::value ? di.occ_float : di.occ_int;
+  const int occ = std::is_same<W, FloatW>::value ? di.occ_float
+                  : std::is_same<W, CoreW>::value  ? di.occ_core
+                                                   : di.occ_int;
   int maxwg = di.cus * (occ > 0 ? occ : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
   if (persistent && nwg > maxwg) nwg = maxwg;
@@ -1215,6 +1462,23 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   a.win = (int2*)(base + kCtlBytes + table_bytes(sh));
   a.spill = a.win + (size_t)a.K * (size_t)cap;
   a.far = a.spill + 2 * (size_t)cap;
+  {
+    size_t off = kCtlBytes + table_bytes(sh) + ((size_t)a.K + 4) * (size_t)cap * sizeof(int2);
+    off = (off + 255) & ~(size_t)255;
+    a.lazy = r.update == OG_LAZY_UPDATE;
+    a.aux = nullptr;
+    a.buf = nullptr;
+    a.buf_cap = 0;
+    a.mark = nullptr;
+    if (a.lazy) {
+      a.aux = (int*)(base + off);
+      off += vec_bytes(a.n);
+      a.buf = (int*)(base + off);
+      off += vec_bytes(a.n);
+      a.buf_cap = (unsigned)a.n;
+    }
+    if (sh.core) a.mark = (int*)(base + off);
+  }
 
   const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
   if (timing) (void)hipEventRecord(t_timers.ev[0], stream);
@@ -1232,11 +1496,17 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   }
   const int fill_grid = di.cus * 8;
   const int src_grid = (sh.nsrc + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int)W::kInfBits);
-  hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
-  hipLaunchKernelGGL(k_init_sources<W>, dim3(src_grid), dim3(kBlock), 0, stream, a);
+  if constexpr (std::is_same<W, CoreW>::value) {
+    hipLaunchKernelGGL(k_zero_ctl, dim3(16), dim3(kBlock), 0, stream, a.ctl);
+    hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
+    hipLaunchKernelGGL(k_init_core, dim3(fill_grid), dim3(kBlock), 0, stream, a);
+  } else {
+    hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int)W::kInfBits);
+    hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
+    hipLaunchKernelGGL(k_init_sources<W>, dim3(src_grid), dim3(kBlock), 0, stream, a);
+  }
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);
-  if (r.flags & OG_FLAG_VALIDATE)
+  if (!std::is_same<W, CoreW>::value && (r.flags & OG_FLAG_VALIDATE))
     hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
   if (timing) (void)hipEventRecord(t_timers.ev[1], stream);
@@ -1254,7 +1524,10 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     long long launched = 0;
     const long long cap_launches = r.max_rounds > 0 ? (long long)r.max_rounds + group : (1LL << 40);
     while (!done && launched < cap_launches) {
-      for (int i = 0; i < group; ++i) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a);
+      for (int i = 0; i < group; ++i) {
+        hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 0);
+        if (a.lazy) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 1);
+      }
       launched += group;
       unsigned hd[64];  // the Control line and the status line
       if (hipMemcpyAsync(hd, a.ctl, sizeof(hd), hipMemcpyDeviceToHost, stream) != hipSuccess)
@@ -1265,7 +1538,9 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     }
   }
   if (timing) (void)hipEventRecord(t_timers.ev[2], stream);
-  if (pred) {
+  if constexpr (std::is_same<W, CoreW>::value) {
+    if (stats) hipLaunchKernelGGL(k_pred_edges<IntW>, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
+  } else if (pred) {
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n, kInf);
     hipLaunchKernelGGL(k_pred_edges<W>, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
     hipLaunchKernelGGL(k_pred_fix, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n);
@@ -1471,6 +1746,29 @@ og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const
                      pending);
   if (hipGetLastError() != hipSuccess) return OG_ERR_HIP;
   return OG_OK;
+}
+
+size_t og_workspace_bytes_kcore(const og_graph* g, const og_schedule* s) {
+  if (!og::graph_ok(g, false) || !og::schedule_ok(s)) return 0;
+  og_schedule r = og::resolved(s);
+  r.delta = 1;
+  return og::ws_bytes_for(g, &r, og::Shape{1, g->n, false, true});
+}
+
+og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void* ws, size_t ws_bytes,
+                   og_stats* stats, void* stream) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  auto fail = [&](og_status st) {
+    if (stats) stats->status = st;
+    return st;
+  };
+  if (!og::graph_ok(g, false) || !og::schedule_ok(s) || !core || !ws) return fail(OG_ERR_INVALID_ARG);
+  if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
+  const og::Shape sh{1, g->n, false, true};
+  if (!og::shape_ok(g, sh)) return fail(OG_ERR_INVALID_ARG);
+  og_schedule r = *s;
+  r.delta = 1;  // one bucket per degree value: peeling needs the strict order
+  return og::run<og::CoreW>(g, sh, {}, {}, nullptr, &r, core, nullptr, nullptr, ws, ws_bytes, stats, stream, false);
 }
 
 og_status og_read_stats(const void* ws, og_stats* stats, void* stream) {

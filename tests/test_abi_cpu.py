@@ -71,6 +71,15 @@ def test_workspace_bytes():
     assert b % 256 == 0 and b >= 65536 + (16 + 4) * 1024 * 8
     s2 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000).to_c()
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 65536 + 256 + 12 * 5000 * 8
+    # lazy update: + change flags and change buffer, one int per vertex each
+    s3 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, update=og.OG_LAZY_UPDATE).to_c()
+    vec = (g.n * 4 + 255) // 256 * 256
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s3)) == 65536 + 256 + 12 * 5000 * 8 + 2 * vec
+    # k-core: no source table; + peel marks (and the lazy arrays)
+    base = 65536 + 12 * 5000 * 8
+    base = (base + 255) // 256 * 256
+    assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s2)) == base + vec
+    assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s3)) == base + 3 * vec
     bad = og.Schedule(delta=0).to_c()
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
     g0 = _lib.OgGraph(0, 0, 0x1000, None, None)
@@ -78,7 +87,7 @@ def test_workspace_bytes():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("delta", 0), ("update", 2), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
+    ("delta", 0), ("update", 3), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
     ("max_rounds", -1), ("flags", 8), ("fusion_threshold", -2),
 ])
 def test_invalid_schedule_rejected(field, value):

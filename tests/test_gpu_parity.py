@@ -297,12 +297,14 @@ def test_async_flag_and_read_stats(orc, cfg0):
 
 
 @pytest.mark.slow
-def test_road_full_size_one_source(orc):
-    """Full 4096^2 road-like grid, the benchmark's schedule: bit-exact."""
+@pytest.mark.parametrize("delta", [1024, 1 << 13])
+def test_road_full_size_one_source(orc, delta):
+    """Full 4096^2 road-like grid; Delta 1024 fused persistent is the
+    benchmark's launch configuration: bit-exact."""
     g = gg.road(4096, seed=0)
     dg = og.DeviceGraph.from_host(g, DEV)
     src = int(gg.pick_sources(g, 1, seed=1)[0])
-    say(f"road4096 src={src} delta=2^13 fused")
-    d, p, st = run_sssp(dg, src, og.Schedule(delta=1 << 13))
+    say(f"road4096 src={src} delta={delta} fused")
+    d, p, st = run_sssp(dg, src, og.Schedule(delta=delta))
     assert st["status"] == 0
     assert_exact(orc, g, src, d, p, "road4096")
