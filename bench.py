@@ -108,6 +108,8 @@ def workload_rmat(args) -> int:
             ("sssp", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_EAGER_NO_FUSION,
                                                 flags=og.OG_FLAG_TIMING)),
             ("sssp_fused", None, og.sssp, og.Schedule(delta=args.rmat_delta, flags=og.OG_FLAG_TIMING)),
+            ("sssp_lazy", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
+                                                     flags=og.OG_FLAG_TIMING)),
             ("wbfs", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING))):
         gx = dg if graph_w is None else og.DeviceGraph(dg.row_ptr, dg.col, torch.from_numpy(
             np.ascontiguousarray(graph_w, dtype=np.int32)).to(dev))
@@ -304,6 +306,79 @@ def workload_diff(args) -> int:
     return 0
 
 
+def workload_kcore(args) -> int:
+    """k-core decomposition (section 6.1) of R-MAT (scale --scale, edge
+    factor 16, symmetric) and of the road-like 4096^2 grid, lazy update with
+    the constant-sum count vs eager (compare-and-swap) with and without
+    fusion.  value = ms per decomposition of the R-MAT graph, lazy.  Checks:
+    the certificate (every v keeps >= core[v] neighbours u with core[u] >=
+    core[v]) on the full graphs, computed with plain torch ops; exact parity
+    with the CPU oracle on R-MAT scale 18, where the oracle is also timed."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1911_07260_amd as og
+    dev = torch.device("cuda:0")
+    res = {}
+    modes = (("lazy", og.OG_LAZY_UPDATE), ("eager", og.OG_EAGER_NO_FUSION),
+             ("eager_fused", og.OG_EAGER_WITH_FUSION))
+
+    def certificate(dg, core):
+        src = torch.repeat_interleave(torch.arange(dg.n, device=dev),
+                                      (dg.row_ptr[1:] - dg.row_ptr[:-1]))
+        cl = core.to(torch.int64)
+        strong = cl[dg.col.to(torch.int64)] >= cl[src]
+        support = torch.bincount(src[strong], minlength=dg.n)
+        ok = bool(torch.all(support >= cl).item())
+        del src, strong, support
+        return ok
+
+    for gname, make in ((f"rmat{args.scale}", lambda: gg.rmat(args.scale, 16, seed=0)),
+                        ("road4096", lambda: gg.road(4096, seed=0))):
+        g = make()
+        dg = og.DeviceGraph.from_host(g, dev, weights=False)
+        del g
+        ws = og.Workspace(dev)
+        out = {"n": dg.n, "m": dg.m}
+        for mname, upd in modes:
+            sched = og.Schedule(update=upd, window_buckets=64, flags=og.OG_FLAG_TIMING)
+            og.kcore(dg, sched, ws=ws)  # warm-up
+            torch.cuda.synchronize()
+            reps = 3
+            t = time.perf_counter()
+            for _ in range(reps):
+                core, st = og.kcore(dg, sched, ws=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) / reps * 1e3
+            out[mname] = {"ms": round(ms, 3), "engine_ms": round(st["engine_ms"], 3), "rounds": st["rounds"],
+                          "barriers": st["barriers"], "pushes": st["pushes_global"] + st["pushes_local"],
+                          "max_core": int(core.max().item()), "certificate": certificate(dg, core)}
+            print(f"[bench] kcore {gname} {mname}: {ms:.2f} ms", file=sys.stderr, flush=True)
+        out["lazy_vs_eager_speedup"] = round(out["eager"]["ms"] / out["lazy"]["ms"], 2)
+        res[gname] = out
+        del dg, ws
+        torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        g = gg.rmat(18, 16, seed=0)
+        t = time.perf_counter()
+        want = oracle.get().kcore(g)
+        cpu_s = time.perf_counter() - t
+        dg = og.DeviceGraph.from_host(g, dev, weights=False)
+        parity = all(np.array_equal(og.kcore(dg, og.Schedule(update=u))[0].cpu().numpy(), want) for _, u in modes)
+        cpu = {"value": round(cpu_s * 1e3, 3), "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": f"R-MAT scale 18 (n={g.n}, m={g.m}), minimum-degree peeling with a binary heap",
+               "parity_all_modes": parity}
+    r = res[f"rmat{args.scale}"]
+    print(_line("ms per k-core decomposition, R-MAT", r["lazy"]["ms"], "ms", 3, 1, r["lazy"]["ms"],
+                {"workload": f"k-core of R-MAT scale {args.scale} (edge factor 16, symmetric) and road-like "
+                             "4096^2; lazy constant-sum vs eager updates, 64 window buckets"},
+                higher_is_better=False, results=res, cpu_baseline=cpu), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,7 +394,7 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize-rocpd", metavar="DB")
     ap.add_argument("--counter")
-    ap.add_argument("--workload", default="road", choices=["road", "rmat", "astar", "rgg", "diff"],
+    ap.add_argument("--workload", default="road", choices=["road", "rmat", "astar", "rgg", "diff", "kcore"],
                     help="road (default, the headline line) or one of the extra workloads")
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--rmat-delta", type=int, default=32)
@@ -335,7 +410,7 @@ def main() -> int:
             print("bench.py: one GPU only", file=sys.stderr)
             return 2
         return {"rmat": workload_rmat, "astar": workload_astar, "rgg": workload_rgg,
-                "diff": workload_diff}[args.workload](args)
+                "diff": workload_diff, "kcore": workload_kcore}[args.workload](args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design is described in "
@@ -413,6 +488,7 @@ def main() -> int:
                                               engine=og.OG_ENGINE_HOST_ROUNDS, flags=og.OG_FLAG_TIMING)),
             ("unfused_host_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_NO_FUSION,
                                                 engine=og.OG_ENGINE_HOST_ROUNDS, flags=og.OG_FLAG_TIMING)),
+            ("lazy_persistent", og.Schedule(delta=args.delta, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_TIMING)),
         ):
             sts = []
             torch.cuda.synchronize()
@@ -429,6 +505,7 @@ def main() -> int:
                              "rounds": int(np.mean([s["rounds"] for s in stats]))}
         variants["fused_vs_unfused_speedup"] = round(
             variants["unfused_persistent"]["engine_ms"] / engine_ms, 2)
+        variants["eager_fused_vs_lazy_speedup"] = round(variants["lazy_persistent"]["engine_ms"] / engine_ms, 2)
         # batched: nq queries (the same 8 sources repeated, then fresh ones)
         # in one persistent launch, distances and predecessors for all
         nq = args.batch
