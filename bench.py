@@ -385,7 +385,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=4096)
-    ap.add_argument("--delta", type=int, default=1024)
+    ap.add_argument("--delta", type=int, default=0,
+                    help="bucket width; 0 = the fastest of a sweep over 2^8..2^12 (fused, two sources each)")
     ap.add_argument("--sources", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the unfused / host-driven legs")
@@ -441,7 +442,6 @@ def main() -> int:
     print(f"[bench] graph n={g.n} m={g.m} generated+uploaded in {gen_s:.1f}s; sources {srcs}",
           file=sys.stderr, flush=True)
 
-    fused = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING)
     ws = og.Workspace(dev)
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     pred = torch.empty(g.n, dtype=torch.int32, device=dev)
@@ -449,6 +449,18 @@ def main() -> int:
     def step(i, sched):
         _, _, st = og.sssp(dg, srcs[i % len(srcs)], sched, ws=ws, out_dist=dist, out_pred=pred)
         return st
+
+    sweep = None
+    if args.delta <= 0:
+        # the configuration sweeps Delta; the headline runs at the fastest one
+        sweep = {}
+        for dlt in (256, 512, 1024, 2048, 4096):
+            sch = og.Schedule(delta=dlt, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING)
+            step(0, sch)
+            sweep[dlt] = round(float(np.mean([step(i, sch)["engine_ms"] for i in range(2)])), 3)
+        args.delta = min(sweep, key=sweep.get)
+        print(f"[bench] delta sweep (engine ms): {sweep} -> {args.delta}", file=sys.stderr, flush=True)
+    fused = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING)
 
     for i in range(args.warmup):
         step(i, fused)
@@ -488,6 +500,10 @@ def main() -> int:
                                               engine=og.OG_ENGINE_HOST_ROUNDS, flags=og.OG_FLAG_TIMING)),
             ("unfused_host_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_NO_FUSION,
                                                 engine=og.OG_ENGINE_HOST_ROUNDS, flags=og.OG_FLAG_TIMING)),
+            ("fused_graph_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION,
+                                               engine=og.OG_ENGINE_GRAPH_ROUNDS, flags=og.OG_FLAG_TIMING)),
+            ("unfused_graph_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_NO_FUSION,
+                                                 engine=og.OG_ENGINE_GRAPH_ROUNDS, flags=og.OG_FLAG_TIMING)),
             ("lazy_persistent", og.Schedule(delta=args.delta, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_TIMING)),
         ):
             sts = []
@@ -571,7 +587,8 @@ def main() -> int:
         "config": {
             "workload": f"SSSP on road-like {args.side}x{args.side} grid (p_keep 0.75, 0.1% long-range "
                         f"<=64 steps, w=llround(10*len*U(1,2)), seed 0), {len(srcs)} sources (seed 1)",
-            "n": g.n, "m": g.m, "delta": args.delta, "update": "eager_with_fusion", "engine": "persistent",
+            "n": g.n, "m": g.m, "delta": args.delta, "delta_sweep_engine_ms": sweep,
+            "update": "eager_with_fusion", "engine": "persistent",
             "outputs": "dist + canonical pred",
         },
         "roofline": {

@@ -83,6 +83,10 @@ typedef int32_t og_status;
 #define OG_ENGINE_PERSISTENT 0 /* one cooperative launch, device-wide barrier
                                   between rounds (default)                   */
 #define OG_ENGINE_HOST_ROUNDS 1 /* one kernel launch per round               */
+#define OG_ENGINE_GRAPH_ROUNDS 2 /* as _HOST_ROUNDS, the launches replayed from
+                                   one executable hipGraph of 32 rounds, kept
+                                   per host thread while the call's kernel,
+                                   grid and arguments stay the same          */
 
 /* Borrowed view of a directed CSR graph (device arrays). */
 typedef struct og_graph {
@@ -104,7 +108,8 @@ typedef struct og_schedule {
                                (0 = 1024; capped at the LDS queue, 1024)      */
   int32_t window_buckets;   /* buckets materialised at once, 2..64 (0 = 16);
                                later ones wait in an overflow ("far") queue   */
-  int32_t engine;           /* OG_ENGINE_PERSISTENT (default) / _HOST_ROUNDS  */
+  int32_t engine;           /* OG_ENGINE_PERSISTENT (default), _HOST_ROUNDS or
+                               _GRAPH_ROUNDS                                  */
   int32_t max_rounds;       /* stop with OG_ERR_ROUND_LIMIT after this many
                                rounds (0 = unlimited)                         */
   int32_t workgroups;       /* workgroups to launch (0 = all co-resident)     */

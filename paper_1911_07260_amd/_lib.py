@@ -29,6 +29,7 @@ OG_EAGER_WITH_FUSION = 1
 OG_LAZY_UPDATE = 2
 
 OG_ENGINE_PERSISTENT = 0
+OG_ENGINE_GRAPH_ROUNDS = 2
 OG_ENGINE_HOST_ROUNDS = 1
 
 

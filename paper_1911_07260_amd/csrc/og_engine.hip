@@ -1365,7 +1365,8 @@ bool schedule_ok(const og_schedule* s) {
     return false;
   if (s->fusion_threshold < 0 || s->window_buckets < 0 || s->window_buckets > kKmax) return false;
   if (s->window_buckets == 1) return false;
-  if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS) return false;
+  if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS && s->engine != OG_ENGINE_GRAPH_ROUNDS)
+    return false;
   if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
   if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING)) return false;
   return true;
@@ -1401,6 +1402,68 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   st->barriers = (int64_t)h.c.epoch;
 }
 
+// Executable hipGraph of `group` host-driven rounds (two kernels per lazy
+// round) chained in stream order.  Kept per host thread and reused while the
+// kernel, grid, device and arguments are unchanged (repeated queries on one
+// graph and workspace share them: the per-query sources live in the
+// workspace).  Never destroyed at exit: the runtime may be gone by then.
+struct RoundGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* func = nullptr;
+  int nwg = 0, nodes = 0, dev = -1;
+  Args args;
+};
+thread_local RoundGraph t_round_graph;
+
+template <class W>
+hipGraphExec_t round_graph(const Args& a, int nwg, int group, int dev) {
+  RoundGraph& rg = t_round_graph;
+  const void* f = (const void*)k_round<W>;
+  const int nodes = group * (a.lazy ? 2 : 1);
+  if (rg.exec && rg.func == f && rg.nwg == nwg && rg.nodes == nodes && rg.dev == dev &&
+      std::memcmp(&rg.args, &a, sizeof(Args)) == 0)
+    return rg.exec;
+  if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
+  if (rg.graph) (void)hipGraphDestroy(rg.graph);
+  rg.exec = nullptr;
+  rg.graph = nullptr;
+  hipGraph_t g = nullptr;
+  if (hipGraphCreate(&g, 0) != hipSuccess) return nullptr;
+  hipGraphNode_t prev = nullptr;
+  for (int i = 0; i < nodes; ++i) {
+    Args ac = a;
+    int phase = a.lazy ? (i & 1) : 0;
+    void* kargs[] = {&ac, &phase};
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(f);
+    p.gridDim = dim3(nwg);
+    p.blockDim = dim3(kBlock);
+    p.sharedMemBytes = 0;
+    p.kernelParams = kargs;
+    p.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    if (hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return nullptr;
+    }
+    prev = node;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return nullptr;
+  }
+  rg.graph = g;
+  rg.exec = ex;
+  rg.func = f;
+  rg.nwg = nwg;
+  rg.nodes = nodes;
+  rg.dev = dev;
+  rg.args = a;
+  return ex;
+}
+
 // Common driver.  vsrcs: nsrc virtual source ids; vtgts: reps virtual
 // target ids or empty.  The caller has validated every argument.
 template <class W>
@@ -1434,6 +1497,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   char* base = (char*)ws;
   int* table = (int*)(base + kCtlBytes);
   Args a;
+  std::memset(&a, 0, sizeof(a));  // padding too: cached round graphs compare arguments bytewise
   a.row_ptr = (const long long*)g->row_ptr;
   a.col = g->col;
   a.w = g->w;
@@ -1518,15 +1582,25 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       return fail(OG_ERR_HIP);
   } else {
     // Launch rounds in groups and poll the done flag between groups; a
-    // launch after completion returns at once.
+    // launch after completion returns at once.  OG_ENGINE_GRAPH_ROUNDS
+    // replays one executable hipGraph holding the group's launches.
     const int group = 32;
     int done = 0;
     long long launched = 0;
     const long long cap_launches = r.max_rounds > 0 ? (long long)r.max_rounds + group : (1LL << 40);
+    hipGraphExec_t exec = nullptr;
+    if (r.engine == OG_ENGINE_GRAPH_ROUNDS) {
+      exec = round_graph<W>(a, nwg, group, dev);
+      if (!exec) return fail(OG_ERR_HIP);
+    }
     while (!done && launched < cap_launches) {
-      for (int i = 0; i < group; ++i) {
-        hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 0);
-        if (a.lazy) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 1);
+      if (exec) {
+        if (hipGraphLaunch(exec, stream) != hipSuccess) return fail(OG_ERR_HIP);
+      } else {
+        for (int i = 0; i < group; ++i) {
+          hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 0);
+          if (a.lazy) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 1);
+        }
       }
       launched += group;
       unsigned hd[64];  // the Control line and the status line

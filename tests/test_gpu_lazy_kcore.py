@@ -51,7 +51,7 @@ def check_sssp(orc, g, src, d, p, tag):
         assert np.array_equal(p.cpu().numpy(), ref_p), f"{tag}: predecessors differ"
 
 
-@pytest.mark.parametrize("engine", [og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS])
+@pytest.mark.parametrize("engine", [og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS, og.OG_ENGINE_GRAPH_ROUNDS])
 @pytest.mark.parametrize("kind,delta", [("grid", 1), ("grid", 16), ("grid", 1 << 20), ("road", 256), ("road", 4096),
                                         ("rmat", 8), ("rmat", 64)])
 def test_lazy_sssp(orc, graphs, kind, delta, engine):
@@ -114,7 +114,7 @@ def run_kcore(dg, **kw):
     return core.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("engine", [og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS])
+@pytest.mark.parametrize("engine", [og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS, og.OG_ENGINE_GRAPH_ROUNDS])
 @pytest.mark.parametrize("update", MODES)
 @pytest.mark.parametrize("kind", ["grid", "road", "rmat"])
 def test_kcore_parity(orc, graphs, kind, update, engine):

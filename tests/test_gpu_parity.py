@@ -59,7 +59,7 @@ def assert_exact(orc, g, src, d, p, tag=""):
         assert np_ == 0, f"{tag}: {np_} predecessors differ"
 
 
-@pytest.mark.parametrize("engine", [og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS])
+@pytest.mark.parametrize("engine", [og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS, og.OG_ENGINE_GRAPH_ROUNDS])
 @pytest.mark.parametrize("update", [og.OG_EAGER_WITH_FUSION, og.OG_EAGER_NO_FUSION])
 @pytest.mark.parametrize("delta", [1, 3, 16, 100, 1024, 1 << 20])
 def test_cfg0_all_schedules(orc, cfg0, engine, update, delta):
@@ -164,7 +164,7 @@ def test_queue_overflow_is_reported(road256):
 
 def test_round_limit(cfg0):
     _, dg = cfg0
-    for engine in (og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS):
+    for engine in (og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS, og.OG_ENGINE_GRAPH_ROUNDS):
         say(f"max_rounds=1 engine={engine}")
         d, p, st = run_sssp(dg, 0, og.Schedule(delta=16, max_rounds=1, engine=engine), check=False)
         assert st["status"] == og.OG_ERR_ROUND_LIMIT and st["rounds"] == 1
@@ -294,6 +294,29 @@ def test_async_flag_and_read_stats(orc, cfg0):
     rc = _lib.load().og_read_stats(ctypes.c_void_p(ws.buf.data_ptr()), ctypes.byref(full), None)
     assert rc == 0 and full.rounds > 0 and full.reached_vertices == g.n
     assert_exact(orc, g, 7, d.cpu().numpy(), p.cpu().numpy(), "async")
+
+
+def test_graph_rounds_replayed(orc, road256, cfg0):
+    """The executable round graph is reused across queries on one workspace
+    (only the sources change) and rebuilt when the graph or schedule
+    changes; every replay must match the oracle, with ordinary persistent
+    launches and synchronisations in between."""
+    g, dg = road256
+    ws = og.Workspace(DEV)
+    sched = og.Schedule(delta=512, engine=og.OG_ENGINE_GRAPH_ROUNDS)
+    for i, src in enumerate(gg.pick_sources(g, 6, seed=21)):
+        say(f"graph rounds replay {i} src={src}")
+        d, p, st = og.sssp(dg, int(src), sched, ws=ws)
+        torch.cuda.synchronize()
+        assert_exact(orc, g, int(src), d.cpu().numpy(), p.cpu().numpy(), f"graph replay {i}")
+        d2, p2, _ = og.sssp(dg, int(src), og.Schedule(delta=512), ws=og.Workspace(DEV))
+        torch.cuda.synchronize()
+        assert torch.equal(d, d2) and torch.equal(p, p2)
+    g0, dg0 = cfg0
+    for upd in (og.OG_EAGER_NO_FUSION, og.OG_LAZY_UPDATE, og.OG_EAGER_WITH_FUSION):
+        say(f"graph rounds rebuild cfg0 update={upd}")
+        d, p, st = run_sssp(dg0, 17, og.Schedule(delta=16, update=upd, engine=og.OG_ENGINE_GRAPH_ROUNDS), ws=ws)
+        assert_exact(orc, g0, 17, d, p, f"graph rebuild {upd}")
 
 
 @pytest.mark.slow
