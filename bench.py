@@ -385,8 +385,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=4096)
-    ap.add_argument("--delta", type=int, default=0,
-                    help="bucket width; 0 = the fastest of a sweep over 2^8..2^12 (fused, two sources each)")
+    ap.add_argument("--delta", type=int, default=512,
+                    help="bucket width (512: the fastest of the 2^8..2^14 sweep on this graph); 0 = sweep "
+                         "2^8..2^12 now (fused, two sources each) and run at the fastest")
     ap.add_argument("--sources", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the unfused / host-driven legs")

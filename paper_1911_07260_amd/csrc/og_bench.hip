@@ -1,13 +1,15 @@
-// og_bench: native driver for the road-like SSSP workload through the C ABI.
+// og_bench: native driver for the benchmark workloads through the C ABI.
 //
-// Generates the seeded road-like grid with libgraphgen, uploads it, and runs
-// single-source queries (distances + canonical predecessors) with og_sssp,
-// timing each query's phases with the library's HIP events.  It exists so
-// that profilers can be attached to a plain native process; the Python
-// benchmark (bench.py) runs the same workload, sources and schedule.
+// Generates the seeded road-like grid (or R-MAT) with libgraphgen, uploads
+// it, and runs single-source queries (distances + canonical predecessors)
+// with og_sssp, or k-core decompositions with og_kcore, timing each call's
+// phases with the library's HIP events.  It exists so that profilers can be
+// attached to a plain native process; the Python benchmark (bench.py) runs
+// the same workloads, sources and schedules.
 //
-//   og_bench [--side 4096] [--delta 1024] [--steps 8] [--warmup 2]
-//            [--update fused|unfused] [--engine persistent|host]
+//   og_bench [--graph road|rmat] [--side 4096] [--scale 24] [--delta 512]
+//            [--steps 8] [--warmup 2] [--update fused|unfused|lazy]
+//            [--engine persistent|host|graph] [--window K] [--kcore]
 //            [--copy-calibration]
 //
 // --copy-calibration instead runs a plain copy kernel over 1 GiB three
@@ -25,6 +27,8 @@
 extern "C" {
 // libgraphgen (graphgen/graphgen.cpp)
 void* gg_road(int32_t side, double p_keep, double lr_frac, int32_t lr_radius, uint64_t seed);
+void* gg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c, int32_t wlo, int32_t whi,
+             uint64_t seed);
 int32_t gg_n(const void* g);
 int64_t gg_m(const void* g);
 void gg_copy(const void* g, int64_t* row_ptr, int32_t* col, int32_t* w);
@@ -68,8 +72,9 @@ int copy_calibration() {
 }  // namespace
 
 int main(int argc, char** argv) {
-  int side = 4096, delta = 1024, steps = 8, warmup = 2, nsrc = 8;
+  int side = 4096, scale = 24, delta = 512, steps = 8, warmup = 2, nsrc = 8, window = 0;
   int update = OG_EAGER_WITH_FUSION, engine = OG_ENGINE_PERSISTENT;
+  bool rmat = false, kcore = false;
   for (int i = 1; i < argc; ++i) {
     auto next = [&](void) -> const char* {
       if (i + 1 >= argc) { std::fprintf(stderr, "missing value for %s\n", argv[i]); std::exit(2); }
@@ -79,13 +84,27 @@ int main(int argc, char** argv) {
     else if (!std::strcmp(argv[i], "--delta")) delta = std::atoi(next());
     else if (!std::strcmp(argv[i], "--steps")) steps = std::atoi(next());
     else if (!std::strcmp(argv[i], "--warmup")) warmup = std::atoi(next());
-    else if (!std::strcmp(argv[i], "--update")) update = std::strcmp(next(), "unfused") ? OG_EAGER_WITH_FUSION : OG_EAGER_NO_FUSION;
-    else if (!std::strcmp(argv[i], "--engine")) engine = std::strcmp(next(), "host") ? OG_ENGINE_PERSISTENT : OG_ENGINE_HOST_ROUNDS;
+    else if (!std::strcmp(argv[i], "--scale")) scale = std::atoi(next());
+    else if (!std::strcmp(argv[i], "--window")) window = std::atoi(next());
+    else if (!std::strcmp(argv[i], "--kcore")) kcore = true;
+    else if (!std::strcmp(argv[i], "--graph")) rmat = !std::strcmp(next(), "rmat");
+    else if (!std::strcmp(argv[i], "--update")) {
+      const char* u = next();
+      update = !std::strcmp(u, "unfused") ? OG_EAGER_NO_FUSION
+               : !std::strcmp(u, "lazy")  ? OG_LAZY_UPDATE
+                                          : OG_EAGER_WITH_FUSION;
+    } else if (!std::strcmp(argv[i], "--engine")) {
+      const char* e = next();
+      engine = !std::strcmp(e, "host") ? OG_ENGINE_HOST_ROUNDS
+               : !std::strcmp(e, "graph") ? OG_ENGINE_GRAPH_ROUNDS
+                                          : OG_ENGINE_PERSISTENT;
+    }
     else if (!std::strcmp(argv[i], "--copy-calibration")) return copy_calibration();
     else { std::fprintf(stderr, "unknown argument %s\n", argv[i]); return 2; }
   }
 
-  void* h = gg_road(side, 0.75, 0.001, 64, 0);
+  // road: as graphgen.road(side, seed=0); rmat: as graphgen.rmat(scale, 16, seed=0), w in [1, 1000)
+  void* h = rmat ? gg_rmat(scale, 16, 0.57, 0.19, 0.19, 1, 1000, 0) : gg_road(side, 0.75, 0.001, 64, 0);
   if (!h) { std::fprintf(stderr, "graph generation failed\n"); return 1; }
   const int32_t n = gg_n(h);
   const int64_t m = gg_m(h);
@@ -98,7 +117,7 @@ int main(int argc, char** argv) {
   for (int32_t v = 0; v < n; ++v)
     if (row_ptr[v + 1] > row_ptr[v]) cand.push_back(v);
   std::vector<int64_t> pick(nsrc);
-  gg_uniform(1, kStreamSources, nsrc, cand.size(), pick.data());
+  gg_uniform(rmat ? 2 : 1, kStreamSources, nsrc, cand.size(), pick.data());
   std::vector<int32_t> srcs(nsrc);
   for (int i = 0; i < nsrc; ++i) srcs[i] = (int32_t)cand[pick[i]];
 
@@ -120,7 +139,8 @@ int main(int argc, char** argv) {
   s.update = update;
   s.engine = engine;
   s.flags = OG_FLAG_TIMING;
-  const size_t wsb = og_workspace_bytes(&g, &s);
+  if (window > 0) s.window_buckets = window;
+  const size_t wsb = kcore ? og_workspace_bytes_kcore(&g, &s) : og_workspace_bytes(&g, &s);
   void* ws = nullptr;
   CHECK(hipMalloc(&ws, wsb));
   hipStream_t stream;
@@ -129,9 +149,10 @@ int main(int argc, char** argv) {
   double eng = 0, pred = 0, tot_e = 0, rounds = 0;
   for (int i = 0; i < warmup + steps; ++i) {
     og_stats st;
-    const og_status rc = og_sssp(&g, srcs[i % nsrc], &s, d_dist, d_pred, ws, wsb, &st, stream);
+    const og_status rc = kcore ? og_kcore(&g, &s, d_dist, ws, wsb, &st, stream)
+                               : og_sssp(&g, srcs[i % nsrc], &s, d_dist, d_pred, ws, wsb, &st, stream);
     if (rc != OG_OK) {
-      std::fprintf(stderr, "og_sssp failed: %s\n", og_status_string(rc));
+      std::fprintf(stderr, "%s failed: %s\n", kcore ? "og_kcore" : "og_sssp", og_status_string(rc));
       return 1;
     }
     if (i >= warmup) {
@@ -143,11 +164,11 @@ int main(int argc, char** argv) {
                    srcs[i % nsrc], st.engine_ms, st.pred_ms, (long long)st.rounds);
     }
   }
-  std::printf("{\"side\": %d, \"n\": %d, \"m\": %lld, \"delta\": %d, \"update\": \"%s\", \"engine\": \"%s\", "
-              "\"steps\": %d, \"engine_ms\": %.4f, \"pred_ms\": %.4f, \"rounds\": %.1f, \"reached_edges\": %.0f}\n",
-              side, n, (long long)m, delta, update == OG_EAGER_WITH_FUSION ? "fused" : "unfused",
-              engine == OG_ENGINE_PERSISTENT ? "persistent" : "host", steps, eng / steps, pred / steps,
-              rounds / steps, tot_e / steps);
+  std::printf("{\"graph\": \"%s\", \"call\": \"%s\", \"n\": %d, \"m\": %lld, \"delta\": %d, \"update\": %d, "
+              "\"engine\": %d, \"steps\": %d, \"engine_ms\": %.4f, \"pred_ms\": %.4f, \"rounds\": %.1f, "
+              "\"reached_edges\": %.0f}\n",
+              rmat ? "rmat" : "road", kcore ? "og_kcore" : "og_sssp", n, (long long)m, delta, update, engine, steps,
+              eng / steps, pred / steps, rounds / steps, tot_e / steps);
   CHECK(hipStreamDestroy(stream));
   CHECK(hipFree(ws));
   CHECK(hipFree(d_rp));
