@@ -415,8 +415,7 @@ def main() -> int:
                 "diff": workload_diff, "kcore": workload_kcore}[args.workload](args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU design is described in "
-              "DESIGN.md and no multi-GPU figure is produced", file=sys.stderr)
+        print("bench.py: one GPU only; no multi-GPU figure is produced", file=sys.stderr)
         return 2
 
     import numpy as np
