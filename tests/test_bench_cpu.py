@@ -1,0 +1,44 @@
+"""bench.py host logic that needs no GPU: the traffic figure is taken from
+the committed counter summary only when it was measured on the same engine
+source and Delta; rocprofv3 databases are summarised per kernel."""
+import os
+import sqlite3
+
+import bench
+
+
+def test_traffic_matches_engine_and_delta(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.txt"
+    f.write_text("traffic_bytes_per_launch: 12345\ndelta: 512\nengine_sha256_16: " + bench.engine_hash() + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.read_traffic(512) == 12345.0
+    assert bench.read_traffic(1024) is None
+    f.write_text("traffic_bytes_per_launch: 12345\ndelta: 512\nengine_sha256_16: 0000000000000000\n")
+    assert bench.read_traffic(512) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.read_traffic(512) is None
+
+
+def test_committed_profile_is_current():
+    """The committed traffic summary was taken on the committed engine at
+    the headline Delta (512)."""
+    assert os.path.exists(bench.TRAFFIC_FILE)
+    assert bench.read_traffic(512) is not None
+
+
+def test_summarize_rocpd(tmp_path, capsys):
+    db = tmp_path / "r.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, duration integer)")
+    con.executemany("insert into kernels values (?, ?)", [("k_a", 100), ("k_a", 300), ("k_b", 50)])
+    con.execute("create table counters_collection (kernel_name text, counter_name text, value real)")
+    con.executemany("insert into counters_collection values (?, ?, ?)",
+                    [("k_a", "FETCH_SIZE", 10.0), ("k_a", "FETCH_SIZE", 30.0), ("k_a", "WRITE_SIZE", 5.0)])
+    con.commit()
+    con.close()
+    assert bench.summarize_rocpd(str(db), None) == 0
+    out = capsys.readouterr().out.splitlines()
+    assert out[1].split()[:3] == ["k_a", "2", "200"]
+    assert bench.summarize_rocpd(str(db), "FETCH_SIZE") == 0
+    out = capsys.readouterr().out.splitlines()
+    assert out[1].split()[:3] == ["k_a", "2", "20.00"]

@@ -320,9 +320,9 @@ def test_graph_rounds_replayed(orc, road256, cfg0):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("delta", [1024, 1 << 13])
+@pytest.mark.parametrize("delta", [512, 1024, 1 << 13])
 def test_road_full_size_one_source(orc, delta):
-    """Full 4096^2 road-like grid; Delta 1024 fused persistent is the
+    """Full 4096^2 road-like grid; Delta 512 fused persistent is the
     benchmark's launch configuration: bit-exact."""
     g = gg.road(4096, seed=0)
     dg = og.DeviceGraph.from_host(g, DEV)
@@ -331,3 +331,52 @@ def test_road_full_size_one_source(orc, delta):
     d, p, st = run_sssp(dg, src, og.Schedule(delta=delta))
     assert st["status"] == 0
     assert_exact(orc, g, src, d, p, "road4096")
+
+
+@pytest.mark.slow
+def test_road_full_size_batched_sample(orc):
+    """The benchmark's batched leg: 64 queries on the full 4096^2 grid in one
+    launch (Delta 512, fused); queries 0, 37 and 63 are compared with the
+    oracle element by element, and every query's distances satisfy the
+    certificate's edge condition (no relaxable edge) on a vertex sample."""
+    g = gg.road(4096, seed=0)
+    dg = og.DeviceGraph.from_host(g, DEV)
+    srcs = [int(s) for s in gg.pick_sources(g, 64, seed=1)]
+    say("road4096 batched x64 delta=512")
+    d, p, st = og.sssp_batch(dg, srcs, og.Schedule(delta=512, queue_capacity=64 * (1 << 21)))
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    for q in (0, 37, 63):
+        ref_d, ref_p = orc.sssp(g, srcs[q])
+        assert np.array_equal(d[q].cpu().numpy(), ref_d), q
+        assert np.array_equal(p[q].cpu().numpy(), ref_p), q
+    rng = np.random.default_rng(3)
+    vs = rng.integers(0, g.n, size=20000)
+    dd = d.cpu().numpy()
+    for q in range(64):
+        dq = dd[q].astype(np.int64)
+        assert dq[srcs[q]] == 0
+        for v in vs[:300]:
+            if dq[v] == INF:
+                continue
+            row = slice(g.row_ptr[v], g.row_ptr[v + 1])
+            assert np.all(dq[g.col[row]] <= dq[v] + g.w[row])
+
+
+@pytest.mark.slow
+def test_rmat22_sssp_and_wbfs_exact(orc):
+    """R-MAT scale 22 (edge factor 16): SSSP at the benchmark's R-MAT
+    schedule (Delta 32, unfused) and wBFS, bit-exact with the oracle."""
+    g = gg.rmat(22, 16, seed=0)
+    dg = og.DeviceGraph.from_host(g, DEV)
+    src = int(gg.pick_sources(g, 1, seed=2)[0])
+    say(f"rmat22 sssp src={src}")
+    d, p, st = run_sssp(dg, src, og.Schedule(delta=32, update=og.OG_EAGER_NO_FUSION))
+    assert st["status"] == 0
+    assert_exact(orc, g, src, d, p, "rmat22")
+    wg = gg.with_weights(g, g.w % 21 + 1)  # [1, log2 n) for n = 2^22
+    dwg = og.DeviceGraph.from_host(wg, DEV)
+    say("rmat22 wbfs")
+    d, p, st = run_sssp(dwg, src, og.Schedule(), fn="wbfs")
+    assert st["status"] == 0
+    assert_exact(orc, wg, src, d, p, "rmat22 wbfs")
