@@ -545,31 +545,43 @@ def main() -> int:
     cpu = None
     parity = None
     if not args.no_cpu:
+        import concurrent.futures as cf
+
         import oracle
         orc = oracle.get()
-        ncpu = min(args.cpu_sources, len(srcs))
-        tot_e = 0
-        parity = True
-        t = time.perf_counter()
-        refs = []
-        for i in range(ncpu):
-            d_ref, p_ref = orc.sssp(g, srcs[i])
-            refs.append((d_ref, p_ref))
-        cpu_s = time.perf_counter() - t
         deg = g.degrees()
-        for i in range(ncpu):
-            d_ref, p_ref = refs[i]
-            tot_e += int(deg[d_ref != og.INF].sum())
+
+        def reached_edges(d_ref):
+            return int(deg[d_ref != og.INF].sum())
+
+        # one core: the first cpu_sources sources in turn
+        ncpu = min(args.cpu_sources, len(srcs))
+        t = time.perf_counter()
+        serial = [orc.sssp(g, srcs[i]) for i in range(ncpu)]
+        serial_s = time.perf_counter() - t
+        serial_gteps = sum(reached_edges(d) for d, _ in serial) / serial_s / 1e9
+        del serial
+        # throughput: every source of the workload at once, one host thread
+        # each (the oracle's C calls run without the interpreter lock)
+        nthreads = min(len(srcs), os.cpu_count() or 1)
+        t = time.perf_counter()
+        with cf.ThreadPoolExecutor(nthreads) as ex:
+            refs = list(ex.map(lambda s_: orc.sssp(g, s_), srcs))
+        par_s = time.perf_counter() - t
+        par_e = sum(reached_edges(d) for d, _ in refs)
+        parity = True
+        for i, (d_ref, p_ref) in enumerate(refs):
             step(i, fused)
             torch.cuda.synchronize()
             parity &= bool(np.array_equal(dist.cpu().numpy(), d_ref)) and bool(
                 np.array_equal(pred.cpu().numpy(), p_ref))
-        cpu = {"value": round(tot_e / cpu_s / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"{ncpu} of the {len(srcs)} sources on the full {args.side}x{args.side} graph, "
-                         f"serial binary-heap Dijkstra + canonical predecessors, {cpu_s:.1f} s",
-               "seconds": round(cpu_s, 2)}
-        print(f"[bench] cpu oracle {cpu_s:.1f}s for {ncpu} sources; parity={parity}", file=sys.stderr,
-              flush=True)
+        cpu = {"value": round(par_e / par_s / 1e9, 5), "unit": "GTEPS", "cores": nthreads, "kind": "oracle",
+               "sample": f"the {len(srcs)} sources of the workload on the full {args.side}x{args.side} graph at "
+                         f"once, one host thread each, binary-heap Dijkstra + canonical predecessors, "
+                         f"{par_s:.1f} s; one core: {ncpu} sources in {serial_s:.1f} s",
+               "seconds": round(par_s, 2), "serial_value": round(serial_gteps, 5), "serial_cores": 1}
+        print(f"[bench] cpu oracle: {len(srcs)} sources on {nthreads} threads in {par_s:.1f}s, one core "
+              f"{serial_gteps:.4f} GTEPS; parity over all sources={parity}", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC,

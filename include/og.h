@@ -31,6 +31,10 @@
  *     directions.  Weights are int32 >= 0.  A negative weight on an edge the
  *     search examines is reported as OG_ERR_NEGATIVE_WEIGHT (outputs then
  *     undefined); OG_FLAG_VALIDATE checks every weight before running.
+ *     Column indices must lie in [0, n) and row_ptr must run from 0 to m
+ *     without decreasing: a malformed graph is undefined behaviour unless
+ *     OG_FLAG_VALIDATE is set, which checks the structure first and then
+ *     returns OG_ERR_INVALID_ARG with nothing else run.
  *   - Distances are int32 with INF = INT32_MAX for unreachable vertices.  A
  *     finite path length that does not fit below INT32_MAX is reported as
  *     OG_ERR_OVERFLOW (the outputs are then undefined).
@@ -62,7 +66,9 @@ typedef int32_t og_status;
 #define OG_ERR_ROUND_LIMIT (-6)     /* schedule.max_rounds reached              */
 
 /* Schedule flags. */
-#define OG_FLAG_VALIDATE 1u /* scan weights for negatives before running      */
+#define OG_FLAG_VALIDATE 1u /* check the CSR structure and the weights' signs
+                               before running (waits for the check, also with
+                               OG_FLAG_ASYNC)                                 */
 #define OG_FLAG_ASYNC 2u    /* do not wait; read the status later with
                                og_read_stats() after synchronising the stream */
 #define OG_FLAG_TIMING 4u   /* time the phases with HIP events recorded on the

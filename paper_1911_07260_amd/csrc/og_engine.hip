@@ -1059,11 +1059,25 @@ __global__ void k_far_min_init(Ctl* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c->far_min[0].v = kNoBucket;
 }
 
-__global__ __launch_bounds__(kBlock) void k_validate(const int* w, long long m, Ctl* ctl) {
+// OG_FLAG_VALIDATE: the CSR structure (row_ptr[0] = 0, non-decreasing,
+// row_ptr[n] = m; every column index in [0, n)) and, when weights are given,
+// their sign (a float32 weight's sign bit reads as a negative int32).
+__global__ __launch_bounds__(kBlock) void k_validate(const long long* row_ptr, int n, const int* col, const int* w,
+                                                      long long m, Ctl* ctl) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  bool bad = false;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) bad |= w[e] < 0;
-  if (__ballot(bad) && lane_id() == 0) atomicExch(reinterpret_cast<int*>(&ctl->status.v), OG_ERR_NEGATIVE_WEIGHT);
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad_w = false, bad_g = false;
+  for (long long e = t0; e < m; e += stride) {
+    bad_g |= (unsigned)col[e] >= (unsigned)n;
+    if (w) bad_w |= w[e] < 0;
+  }
+  for (long long v = t0; v <= n; v += stride) {
+    const long long r = row_ptr[v];
+    bad_g |= v == 0 ? r != 0 : r < row_ptr[v - 1];
+    if (v == n) bad_g |= r != m;
+  }
+  if (__ballot(bad_g) && lane_id() == 0) atomicExch(reinterpret_cast<int*>(&ctl->status.v), OG_ERR_INVALID_ARG);
+  if (__ballot(bad_w) && lane_id() == 0) set_status(ctl, OG_ERR_NEGATIVE_WEIGHT);
 }
 
 // Persistent engine: one cooperative launch; rounds separated by a
@@ -1570,9 +1584,18 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     hipLaunchKernelGGL(k_init_sources<W>, dim3(src_grid), dim3(kBlock), 0, stream, a);
   }
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);
-  if (!std::is_same<W, CoreW>::value && (r.flags & OG_FLAG_VALIDATE))
-    hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, g->w, (long long)g->m, a.ctl);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
+  if (r.flags & OG_FLAG_VALIDATE) {
+    // checked before anything reads the graph's structure; a bad graph
+    // returns here with nothing else launched
+    hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, (const long long*)g->row_ptr, g->n,
+                       g->col, std::is_same<W, CoreW>::value ? nullptr : g->w, (long long)g->m, a.ctl);
+    unsigned hs[32];  // the status line
+    if (hipMemcpyAsync(hs, &a.ctl->status, sizeof(hs), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return fail(OG_ERR_HIP);
+    if (hs[0] != 0) return fail((og_status)(int)hs[0]);
+  }
   if (timing) (void)hipEventRecord(t_timers.ev[1], stream);
 
   if (persistent) {

@@ -187,6 +187,43 @@ def test_negative_weight_reported():
         assert st["status"] == og.OG_ERR_NEGATIVE_WEIGHT
 
 
+def test_validate_rejects_malformed_graphs(orc, cfg0):
+    """OG_FLAG_VALIDATE checks the CSR structure before anything reads it:
+    a column index outside [0, n), a decreasing row_ptr or row_ptr[n] != m
+    is OG_ERR_INVALID_ARG, with the outputs untouched; a valid graph runs."""
+    say("validate malformed graphs")
+    rp = torch.tensor([0, 2, 3, 4], dtype=torch.int64, device=DEV)
+    col = torch.tensor([1, 2, 2, 0], dtype=torch.int32, device=DEV)
+    w = torch.tensor([1, 4, 1, 3], dtype=torch.int32, device=DEV)
+    V = og.OG_FLAG_VALIDATE
+    d, p, st = og.sssp(og.DeviceGraph(rp, col, w), 0, og.Schedule(delta=2, flags=V))
+    torch.cuda.synchronize()
+    assert st["status"] == 0 and d.cpu().tolist() == [0, 1, 2]
+    cases = {
+        "column out of range": (rp, torch.tensor([1, 3, 2, 0], dtype=torch.int32, device=DEV)),
+        "negative column": (rp, torch.tensor([1, -1, 2, 0], dtype=torch.int32, device=DEV)),
+        "decreasing row_ptr": (torch.tensor([0, 3, 2, 4], dtype=torch.int64, device=DEV), col),
+        "row_ptr[0] != 0": (torch.tensor([1, 2, 3, 4], dtype=torch.int64, device=DEV), col),
+        "row_ptr[n] != m": (torch.tensor([0, 2, 3, 3], dtype=torch.int64, device=DEV), col),
+    }
+    for name, (rp_bad, col_bad) in cases.items():
+        say(f"validate: {name}")
+        dg = og.DeviceGraph(rp_bad, col_bad, w)
+        out = torch.full((3,), -7, dtype=torch.int32, device=DEV)
+        d, p, st = og.sssp(dg, 0, og.Schedule(delta=2, flags=V), check=False, out_dist=out)
+        torch.cuda.synchronize()
+        assert st["status"] == og.OG_ERR_INVALID_ARG, name
+        core, st = og.kcore(og.DeviceGraph(rp_bad, col_bad, None), og.Schedule(update=og.OG_LAZY_UPDATE, flags=V),
+                            check=False)
+        torch.cuda.synchronize()
+        assert st["status"] == og.OG_ERR_INVALID_ARG, name
+    wf = torch.tensor([1.0, -2.0, 1.0, 3.0], dtype=torch.float32, device=DEV)
+    say("validate: negative float32 weight")
+    _, _, _, st = og.sssp_f32(og.DeviceGraph(rp, col, w), wf, 0, og.Schedule(delta=2, flags=V), check=False)
+    torch.cuda.synchronize()
+    assert st["status"] == og.OG_ERR_NEGATIVE_WEIGHT
+
+
 def test_tiny_graphs(orc):
     say("tiny graphs")
     cases = [
