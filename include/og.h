@@ -64,6 +64,9 @@ typedef int32_t og_status;
                                        entries per queue would have been used  */
 #define OG_ERR_HIP (-5)             /* a HIP runtime call failed                */
 #define OG_ERR_ROUND_LIMIT (-6)     /* schedule.max_rounds reached              */
+#define OG_ERR_INTERNAL (-7)        /* an internal consistency check failed
+                                       (a library bug; no memory was touched
+                                       out of bounds)                           */
 
 /* Schedule flags. */
 #define OG_FLAG_VALIDATE 1u /* check the CSR structure and the weights' signs
@@ -73,6 +76,15 @@ typedef int32_t og_status;
                                og_read_stats() after synchronising the stream */
 #define OG_FLAG_TIMING 4u   /* time the phases with HIP events recorded on the
                                stream (ignored with OG_FLAG_ASYNC)            */
+#define OG_FLAG_LIGHT_HEAVY 8u /* light/heavy edge split (Meyer and Sanders'
+                               Delta-stepping; the paper relaxes every edge):
+                               rounds relax only light edges (w < Delta); the
+                               heavy edges of the vertices settled in a bucket
+                               are relaxed once, in one extra round when the
+                               bucket is finished.  int32 weights and eager
+                               updates only (og_sssp_f32 and a lazy schedule
+                               return OG_ERR_INVALID_ARG); the workspace holds
+                               a split copy of the rows.  og_kcore ignores it. */
 
 /* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
 #define OG_EAGER_NO_FUSION 0

@@ -19,10 +19,12 @@ OG_ERR_OVERFLOW = -3
 OG_ERR_WORKSPACE = -4
 OG_ERR_HIP = -5
 OG_ERR_ROUND_LIMIT = -6
+OG_ERR_INTERNAL = -7
 
 OG_FLAG_VALIDATE = 1
 OG_FLAG_ASYNC = 2
 OG_FLAG_TIMING = 4
+OG_FLAG_LIGHT_HEAVY = 8
 
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1

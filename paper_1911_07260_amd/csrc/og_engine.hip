@@ -66,7 +66,11 @@ constexpr unsigned kNoBucket = 0xffffffffu;
 constexpr int kInf = INT_MAX;
 constexpr int kPeeled = INT_MAX;  // k-core mark of a peeled vertex (above every generation)
 
-enum : int { kInWin = 0, kInSpill = 1, kInFar = 2 };
+enum : int { kInWin = 0, kInSpill = 1, kInFar = 2, kInHeavy = 3 };
+// Light/heavy split: LDS ring entries carry a vertex's light-edge count with
+// this bit set when the vertex also has heavy edges.
+constexpr int kHeavyBit = 1 << 30;
+constexpr int kDegMask = kHeavyBit - 1;
 enum : int {
   kStRelax, kStImprove, kStPushLocal, kStPushGlobal, kStFar, kStBatches, kStReachedV, kStReachedE, kStChain, kStCount
 };
@@ -93,6 +97,8 @@ struct alignas(128) Control {
   unsigned buckets;
   unsigned epoch;    // device-wide barriers completed
   unsigned far_gen;  // generation of the pending far list (k-core filing)
+  unsigned hout;     // light/heavy split: heavy list receiving settled vertices
+  unsigned hgen;     // light/heavy split: generation of that list (heavy rounds so far)
 };
 
 // Device-side control block at the start of the workspace.
@@ -111,6 +117,8 @@ struct Ctl {
   Word buf_tail;           // lazy update: entries in the change buffer
   Word64 need;
   Word64 st[kStCount];
+  Word heavy_tail[2];  // light/heavy split: settled vertices per heavy list
+  Word big_rows;       // light/heavy split: rows left to the wavefront split pass
 };
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block too large");
 
@@ -144,6 +152,14 @@ struct Args {
   unsigned buf_cap;
   int* mark;      // [n] k-core: kPeeled once peeled, else the newest far-list
                   // generation the vertex was filed in
+  // light/heavy split (SplitW only)
+  const int* ecol;    // [m] the rows' light edges first, then the heavy ones
+  const int* ew;      // [m] their weights
+  const int* lsplit;  // [nbase] light edges per row
+  unsigned* hmark;    // [n] 1 + the generation of the last heavy list holding the vertex
+  int2* heavy;        // 2 lists of hcap (v, 0) entries: vertices settled in a bucket
+  unsigned hcap;
+  long long m;
 };
 
 struct Counters {
@@ -168,6 +184,8 @@ struct Smem {
   // snapshot of the control block for this round
   unsigned cur, in_count, win_hi, round, epoch, far_stamp;
   int in_kind, in_index, done, spill_out, far_out;
+  int hout;       // light/heavy split
+  unsigned hgen;  // light/heavy split
 };
 
 // ------------------------------------------------- device-coherent access
@@ -216,6 +234,7 @@ __device__ __forceinline__ void set_status(Ctl* c, int st) {
 // with +inf = 0x7f800000 as the unreachable label).
 struct IntW {
   static constexpr int kInfBits = INT_MAX;
+  static constexpr bool kSplit = false;
   // nd = d + w; false (and a status) for a negative weight or a sum that
   // reaches INT32_MAX
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
@@ -243,6 +262,7 @@ struct IntW {
 
 struct FloatW {
   static constexpr int kInfBits = 0x7f800000;  // +inf
+  static constexpr bool kSplit = false;
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
     const float w = __int_as_float(wraw);
     if (!(w >= 0.0f) || w == __int_as_float(kInfBits)) {  // negative, NaN or infinite
@@ -272,6 +292,16 @@ struct FloatW {
 // k-core: the priority of a vertex is its remaining degree (the "dist"
 // array is the priority vector), one bucket per value; no weights.
 struct CoreW : IntW {};
+
+// Light/heavy split (Meyer and Sanders' Delta-stepping; the paper relaxes
+// every edge): int32 distances, rounds relax the light edges (w < Delta)
+// only, and the heavy edges of the vertices settled in a bucket are relaxed
+// once, in one extra round when the bucket is finished.  A separate
+// instantiation, so the other engines' code is not touched by it.
+struct SplitW : IntW {
+  static constexpr bool kSplit = true;
+  __device__ static bool light(const Args& a, int wraw) { return wraw < (int)a.delta; }
+};
 
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
   int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
@@ -369,6 +399,28 @@ __device__ void wave_append_buf(const Args& a, bool has, int v) {
   }
 }
 
+// Light/heavy split: files the lanes' vertices (processed in the current
+// bucket, with heavy edges) in the pending heavy list, each at most once per
+// list (the generation stamp in hmark).  The stamp is per list, not per
+// bucket: with an A* estimate a heavy edge can lead back into the current
+// bucket, so a vertex whose heavy edges were relaxed in the bucket's heavy
+// round can improve again and must be filed again.  One atomic per wavefront.
+__device__ void wave_append_heavy(const Args& a, const Smem& s, bool has, int v) {
+  const unsigned stamp = s.hgen + 1u;
+  if (has) has = atomicMax(&a.hmark[v], stamp) < stamp;
+  const unsigned long long m = __ballot(has);
+  if (m == 0) return;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(&a.ctl->heavy_tail[s.hout].v, (unsigned)__popcll(m));
+  base = __shfl(base, leader);
+  if (has) {
+    const unsigned pos = base + (unsigned)__popcll(m & lanemask_lt());
+    if (pos < a.hcap) st_entry(a.heavy + (size_t)s.hout * a.hcap, pos, v, 0);
+    else set_status(a.ctl, OG_ERR_WORKSPACE);
+  }
+}
+
 // Routes one improved vertex per lane: the current bucket goes to the LDS
 // ring when fusing, together with its CSR row so the next hop needs no row
 // lookup (falling back to the spill list when the ring is full); later
@@ -408,24 +460,48 @@ __device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v,
 // dependent global round trips per hop (edge loads, then the atomic
 // together with the next vertex's row).  Otherwise (a global list) the row
 // is looked up per entry.
+//
+// SplitW (light/heavy split): an ordinary round relaxes a vertex's light
+// edges and files the vertex (once per bucket) for the bucket's heavy round;
+// the heavy round (input kind kInHeavy) relaxes the heavy part of each filed
+// vertex's row at its final distance.  Rows and list entries are checked on
+// this path: a violated bound is OG_ERR_INTERNAL, never an access.
 template <class W>
 __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds) {
   const int tid = threadIdx.x;
-  const int v = ent.x, d = ent.y;
+  const int v = ent.x;
+  // a heavy-round entry uses the vertex's final distance
+  const int d = W::kSplit && v >= 0 && !from_lds && s.in_kind == kInHeavy
+                    ? (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + v)
+                    : ent.y;
   int deg = 0, start = 0, voff = 0;
-  bool repush = false;
+  bool repush = false, settle = false;
   unsigned rb = 0;
   if (v >= 0) {
     const int vb = a.reps == 1 ? v : (int)((unsigned)v % (unsigned)a.nbase);
     voff = v - vb;
     if (from_lds) {
       start = ent.z;
-      deg = ent.w;
+      if constexpr (W::kSplit) {
+        deg = ent.w & kDegMask;
+        settle = (ent.w & kHeavyBit) != 0;
+      } else {
+        deg = ent.w;
+      }
+    } else if (W::kSplit && s.in_kind == kInHeavy) {
+      // the bucket is finished: the heavy part of the vertex's row
+      const long long r0 = a.row_ptr[vb];
+      const long long r1 = a.row_ptr[vb + 1];
+      const int l = a.lsplit[vb];
+      start = (int)r0 + l;
+      deg = (int)(r1 - r0) - l;
     } else {
       // issued together: the staleness check does not delay the row lookup
       const int cv = a.dist[v];
       const long long r0 = a.row_ptr[vb];
       const long long r1 = a.row_ptr[vb + 1];
+      int l = 0;
+      if constexpr (W::kSplit) l = a.lsplit[vb];
       const unsigned key = W::key(a, v, d);
       bool live = d <= cv;
       if (live) {
@@ -438,7 +514,20 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
       if (live && a.tgts && key >= (unsigned)s.tb[query_of(a, v)]) live = false;  // cannot improve the target
       if (live) {
         start = (int)r0;
-        deg = (int)(r1 - r0);
+        if constexpr (W::kSplit) {
+          deg = l;
+          settle = (int)(r1 - r0) > l;
+        } else {
+          deg = (int)(r1 - r0);
+        }
+      }
+    }
+    if constexpr (W::kSplit) {
+      if ((unsigned)v >= (unsigned)a.n || start < 0 || deg < 0 || (long long)start + deg > a.m) {
+        set_status(a.ctl, OG_ERR_INTERNAL);
+        deg = 0;
+        settle = false;
+        repush = false;
       }
     }
   }
@@ -447,6 +536,7 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
     if (repush) tgt = rb < s.win_hi ? (int)(rb & (unsigned)(a.K - 1)) : a.K + 1;
     wave_push_global(a, s, c, repush, tgt, v, d, rb);
   }
+  if constexpr (W::kSplit) wave_append_heavy(a, s, settle, v);  // heavy edges wait for the bucket's end
   int total;
   const int off = block_excl_scan(deg, s, &total);
   s.boff[tid] = off;
@@ -476,8 +566,8 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
       }
       const int edge = s.bstart[lo] + (e - s.boff[lo]);
       const int dsrc = s.bd[lo];
-      const int ub = a.col[edge];
-      const int wt = a.w[edge];
+      const int ub = W::kSplit ? a.ecol[edge] : a.col[edge];
+      const int wt = W::kSplit ? a.ew[edge] : a.w[edge];
       const int dnow = from_lds ? a.dist[s.bv[lo]] : dsrc;
       u = ub + s.bvo[lo];
       c.relax++;
@@ -491,10 +581,12 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
           b = W::bucket(a, key);
           if (b < cur) b = cur;  // only an inconsistent A* estimate gets here
           long long q0 = 0, q1 = 0;
+          int ql = 0;
           const bool chase = a.fused && b == cur;
           if (chase) {  // the next hop's row, fetched alongside the atomic
             q0 = a.row_ptr[ub];
             q1 = a.row_ptr[ub + 1];
+            if constexpr (W::kSplit) ql = a.lsplit[ub];
           }
           const int old = atomicMin(&a.dist[u], (int)nd);
           if ((int)nd < old) {
@@ -502,6 +594,7 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
             has = true;
             r0 = (int)q0;
             rdeg = (int)(q1 - q0);
+            if constexpr (W::kSplit) rdeg = ql | (rdeg > ql ? kHeavyBit : 0);
           }
         }
       }
@@ -695,7 +788,8 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
 template <class W>
 __device__ void run_round(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
-  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const int2* in = W::kSplit && s.in_kind == kInHeavy ? a.heavy + (size_t)s.in_index * a.hcap
+                                                      : list_ptr(a, s.in_kind, s.in_index);
   const unsigned count = s.in_count;
   const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
   const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
@@ -771,6 +865,7 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
 //   4. otherwise the next non-empty bucket (section 3.2: smallest bucket
 //      across workers), or stop (nothing left, or PPSP / A*: that bucket's
 //      lower bound i*Delta already reaches every target's distance).
+template <class W>
 __device__ void decide(const Args& a) {
   Ctl* c = a.ctl;
   const int lane = (int)lane_id();
@@ -785,6 +880,11 @@ __device__ void decide(const Args& a) {
   const unsigned spill_raw = ld_dev(&c->spill_tail[so].v);
   const unsigned far_raw = ld_dev(&c->far_tail[far_in].v);
   const unsigned fmin = far_raw ? ld_dev(&c->far_min[far_in].v) : kNoBucket;
+  unsigned hout = 0, heavy_raw = 0;
+  if constexpr (W::kSplit) {
+    hout = ld_dev(&c->c.hout);
+    heavy_raw = ld_dev(&c->heavy_tail[hout].v);
+  }
   // window occupancy, lane j looks at bucket cur + j
   unsigned wraw = 0;
   bool nonempty = false;
@@ -817,6 +917,7 @@ __device__ void decide(const Args& a) {
   // the consumed input list is empty again
   if (in_kind == kInWin) st_dev(&c->win_tail[in_index].v, 0);
   else if (in_kind == kInSpill) st_dev(&c->spill_tail[in_index].v, 0);
+  else if (W::kSplit && in_kind == kInHeavy) st_dev(&c->heavy_tail[in_index].v, 0);
   else {
     st_dev(&c->far_tail[in_index].v, 0);
     st_dev(&c->far_min[in_index].v, kNoBucket);
@@ -840,6 +941,7 @@ __device__ void decide(const Args& a) {
   unsigned done = 0;
   unsigned ncur = cur, count = 0, buckets = ld_dev(&c->c.buckets), nwin_hi = win_hi;
   int nkind = kInWin, nindex = 0, nspill_out = so;
+  unsigned nhout = hout;
   if (status != 0) {
     done = 1;
   } else if (a.max_rounds && round >= a.max_rounds) {
@@ -858,6 +960,14 @@ __device__ void decide(const Args& a) {
     nindex = so;
     nspill_out = 1 - so;
     count = clampcap(spill_raw);
+  } else if (W::kSplit && heavy_raw) {
+    // the current bucket is finished: relax the heavy edges of the vertices
+    // settled in it (later buckets, or with an A* estimate possibly this one
+    // again); later filings go to the other list, a new generation
+    nkind = kInHeavy;
+    nindex = (int)hout;
+    nhout = 1u - hout;
+    count = heavy_raw < a.hcap ? heavy_raw : a.hcap;
   } else {
     const unsigned wnext = ne ? cur + (unsigned)(__ffsll((long long)ne) - 1) : kNoBucket;
     const unsigned next = wnext < fmin ? wnext : fmin;
@@ -889,10 +999,15 @@ __device__ void decide(const Args& a) {
   st_dev(&c->c.far_in, (unsigned)far_in);
   st_dev(&c->c.win_hi, nwin_hi);
   st_dev(&c->c.buckets, buckets);
+  if constexpr (W::kSplit) {
+    if (nhout != hout) st_dev(&c->c.hgen, ld_dev(&c->c.hgen) + 1u);
+    st_dev(&c->c.hout, nhout);
+  }
   st_dev(&c->c.done, done);
   st_dev(&c->c.round, round);
 }
 
+template <class W>
 __device__ void load_control(const Args& a, Smem& s) {
   Ctl* c = a.ctl;
   s.cur = ld_dev(&c->c.cur);
@@ -906,6 +1021,10 @@ __device__ void load_control(const Args& a, Smem& s) {
   s.far_out = s.in_kind == kInFar ? 1 - far_in : far_in;
   s.far_stamp = ld_dev(&c->c.far_gen) + (s.in_kind == kInFar ? 1u : 0u);
   s.epoch = ld_dev(&c->c.epoch);
+  if constexpr (W::kSplit) {
+    s.hout = (int)ld_dev(&c->c.hout);
+    s.hgen = ld_dev(&c->c.hgen);
+  }
   s.done = ld_dev(&c->c.done) || ld_dev(&c->status.v) != 0;
 }
 
@@ -917,6 +1036,7 @@ __device__ void load_control(const Args& a, Smem& s) {
 // wave 0) publishes the new barrier count on kFlags release flags.  With
 // wait_others (the persistent engine) every other workgroup spins on one of
 // those flags; the host-driven engine ends the kernel instead.
+template <class W>
 __device__ void round_barrier(const Args& a, Smem& s, Counters& c, bool wait_others, bool decide_next) {
   Ctl* ctl = a.ctl;
   if (threadIdx.x == 0) atomicMax(&ctl->round_max_batches.v, c.round_batches);
@@ -943,7 +1063,7 @@ __device__ void round_barrier(const Args& a, Smem& s, Counters& c, bool wait_oth
   const unsigned next = s.epoch + 1;
   if (s.last) {
     if (threadIdx.x < kWave) {
-      if (decide_next) decide(a);
+      if (decide_next) decide<W>(a);
       if (threadIdx.x == 0) st_dev(&ctl->c.epoch, next);
       wait_vm();
       st_dev(&ctl->flag[threadIdx.x].v, next);
@@ -1008,6 +1128,70 @@ __global__ __launch_bounds__(kBlock) void k_init_sources(Args a) {
     a.dist[s] = 0;
     st_entry(a.far, (size_t)i, s, 0);
     atomicMin(&c->far_min[0].v, W::bucket(a, W::key(a, s, 0)));
+  }
+}
+
+// Light/heavy split of every row: a copy with the light edges (w < Delta)
+// first and the heavy ones after, each group in its original order, and
+// lsplit[v] = light edges of v; hmark is cleared.  Rows of up to
+// kSplitSmall edges are split by one thread; longer rows are listed for
+// k_split_big (one wavefront per row).
+constexpr int kSplitSmall = 64;
+__global__ __launch_bounds__(kBlock) void k_split_small(Args a, int* ecol, int* ew, int* lsplit, int* big) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long v = t0; v < a.n; v += stride) a.hmark[v] = 0u;
+  for (long long v = t0; v < a.nbase; v += stride) {
+    const long long r0 = a.row_ptr[v], r1 = a.row_ptr[v + 1];
+    if (r1 - r0 > kSplitSmall) {
+      big[atomicAdd(&a.ctl->big_rows.v, 1u)] = (int)v;
+      continue;
+    }
+    int l = 0;
+    for (long long e = r0; e < r1; ++e) l += SplitW::light(a, a.w[e]) ? 1 : 0;
+    long long li = r0, hi = r0 + l;
+    for (long long e = r0; e < r1; ++e) {
+      const int c = a.col[e], w = a.w[e];
+      const long long o = SplitW::light(a, w) ? li++ : hi++;
+      ecol[o] = c;
+      ew[o] = w;
+    }
+    lsplit[v] = l;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_big(Args a, int* ecol, int* ew, int* lsplit, const int* big) {
+  const unsigned nbig = a.ctl->big_rows.v;
+  const unsigned lane = lane_id();
+  const unsigned nwave = gridDim.x * (kBlock / kWave);
+  for (unsigned i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < nbig; i += nwave) {
+    const int v = big[i];
+    const long long r0 = a.row_ptr[v], r1 = a.row_ptr[v + 1];
+    long long l = 0;
+    for (long long e0 = r0; e0 < r1; e0 += kWave) {
+      const long long e = e0 + lane;
+      l += __popcll(__ballot(e < r1 && SplitW::light(a, a.w[e])));
+    }
+    long long li = r0, hi = r0 + l;
+    for (long long e0 = r0; e0 < r1; e0 += kWave) {
+      const long long e = e0 + lane;
+      const bool in = e < r1;
+      int c = 0, w = 0;
+      if (in) {
+        c = a.col[e];
+        w = a.w[e];
+      }
+      const bool lt = in && SplitW::light(a, w);
+      const unsigned long long ml = __ballot(lt), mh = __ballot(in && !lt);
+      if (in) {
+        const long long o = lt ? li + __popcll(ml & lanemask_lt()) : hi + __popcll(mh & lanemask_lt());
+        ecol[o] = c;
+        ew[o] = w;
+      }
+      li += __popcll(ml);
+      hi += __popcll(mh);
+    }
+    if (lane == 0) lsplit[v] = (int)l;
   }
 }
 
@@ -1087,16 +1271,16 @@ template <class W>
 __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   __shared__ Smem s;
   Counters c;
-  if (threadIdx.x == 0) load_control(a, s);
+  if (threadIdx.x == 0) load_control<W>(a, s);
   __syncthreads();
   while (!s.done) {
     run_round<W>(a, s, c);
     if (a.lazy) {
-      round_barrier(a, s, c, true, false);
+      round_barrier<W>(a, s, c, true, false);
       run_flush<W>(a, s, c);
     }
-    round_barrier(a, s, c, true, true);
-    if (threadIdx.x == 0) load_control(a, s);
+    round_barrier<W>(a, s, c, true, true);
+    if (threadIdx.x == 0) load_control<W>(a, s);
     __syncthreads();
   }
   flush_counters(a, c);
@@ -1109,15 +1293,15 @@ template <class W>
 __global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
   __shared__ Smem s;
   Counters c;
-  if (threadIdx.x == 0) load_control(a, s);
+  if (threadIdx.x == 0) load_control<W>(a, s);
   __syncthreads();
   if (s.done) return;
   if (phase == 0) {
     run_round<W>(a, s, c);
-    round_barrier(a, s, c, false, !a.lazy);
+    round_barrier<W>(a, s, c, false, !a.lazy);
   } else {
     run_flush<W>(a, s, c);
-    round_barrier(a, s, c, false, true);
+    round_barrier<W>(a, s, c, false, true);
   }
   flush_counters(a, c);
 }
@@ -1277,6 +1461,7 @@ struct DeviceInfo {
   int occ_int = 0;    // co-resident k_persistent<IntW> workgroups per CU
   int occ_float = 0;  // co-resident k_persistent<FloatW> workgroups per CU
   int occ_core = 0;   // co-resident k_persistent<CoreW> workgroups per CU
+  int occ_split = 0;  // co-resident k_persistent<SplitW> workgroups per CU
   int coop = 0;
   bool valid = false;
 };
@@ -1296,6 +1481,8 @@ bool device_info(int dev, DeviceInfo* out) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_float, k_persistent<FloatW>, kBlock, 0) != hipSuccess)
       return false;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_core, k_persistent<CoreW>, kBlock, 0) != hipSuccess)
+      return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_split, k_persistent<SplitW>, kBlock, 0) != hipSuccess)
       return false;
     di.valid = true;
   }
@@ -1357,6 +1544,8 @@ size_t table_bytes(const Shape& sh) {
   return (b + 255) & ~(size_t)255;
 }
 
+bool split_on(const og_schedule* r, const Shape& sh) { return !sh.core && (r->flags & OG_FLAG_LIGHT_HEAVY); }
+
 // Per-vertex int arrays after the queues: lazy change flags / counts and
 // the change buffer (lazy), peel marks (k-core); each 256-byte aligned.
 size_t vec_bytes(long long n) { return ((size_t)n * sizeof(int) + 255) & ~(size_t)255; }
@@ -1369,6 +1558,9 @@ size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   const long long nv = (long long)sh.reps * g->n;
   if (r->update == OG_LAZY_UPDATE) b += 2 * vec_bytes(nv);
   if (sh.core) b += vec_bytes(nv);
+  // light/heavy split: col and w copies, light counts, long-row list, bucket
+  // stamps and two heavy lists of (v, 0) entries
+  if (split_on(r, sh)) b += 2 * vec_bytes(g->m) + 2 * vec_bytes(g->n) + vec_bytes(nv) + 4 * vec_bytes(nv);
   return b;
 }
 
@@ -1382,7 +1574,8 @@ bool schedule_ok(const og_schedule* s) {
   if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS && s->engine != OG_ENGINE_GRAPH_ROUNDS)
     return false;
   if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
-  if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING)) return false;
+  if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY)) return false;
+  if ((s->flags & OG_FLAG_LIGHT_HEAVY) && s->update == OG_LAZY_UPDATE) return false;
   return true;
 }
 
@@ -1498,8 +1691,9 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   if (!device_info(dev, &di)) return fail(OG_ERR_HIP);
   const bool persistent = r.engine == OG_ENGINE_PERSISTENT;
   if (persistent && !di.coop) return fail(OG_ERR_HIP);
-  const int occ = std::is_same<W, FloatW>::value ? di.occ_float
+  const int occ = std::is_same<W, FloatW>::value   ? di.occ_float
                   : std::is_same<W, CoreW>::value  ? di.occ_core
+                  : std::is_same<W, SplitW>::value ? di.occ_split
                                                    : di.occ_int;
   int maxwg = di.cus * (occ > 0 ? occ : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
@@ -1508,6 +1702,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   if (nwg < 1) nwg = 1;
 
   const long long cap = queue_cap(g, &r, sh);
+  int *split_col = nullptr, *split_w = nullptr, *split_l = nullptr, *split_big = nullptr;
   char* base = (char*)ws;
   int* table = (int*)(base + kCtlBytes);
   Args a;
@@ -1555,7 +1750,28 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       off += vec_bytes(a.n);
       a.buf_cap = (unsigned)a.n;
     }
-    if (sh.core) a.mark = (int*)(base + off);
+    if (sh.core) {
+      a.mark = (int*)(base + off);
+      off += vec_bytes(a.n);
+    }
+    a.m = g->m;
+    if constexpr (W::kSplit) {
+      split_col = (int*)(base + off);
+      off += vec_bytes(g->m);
+      split_w = (int*)(base + off);
+      off += vec_bytes(g->m);
+      split_l = (int*)(base + off);
+      off += vec_bytes(g->n);
+      split_big = (int*)(base + off);
+      off += vec_bytes(g->n);
+      a.hmark = (unsigned*)(base + off);
+      off += vec_bytes(a.n);
+      a.heavy = (int2*)(base + off);
+      a.hcap = (unsigned)a.n;
+      a.ecol = split_col;
+      a.ew = split_w;
+      a.lsplit = split_l;
+    }
   }
 
   const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
@@ -1595,6 +1811,12 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
         hipStreamSynchronize(stream) != hipSuccess)
       return fail(OG_ERR_HIP);
     if (hs[0] != 0) return fail((og_status)(int)hs[0]);
+  }
+  if constexpr (W::kSplit) {
+    hipLaunchKernelGGL(k_split_small, dim3(fill_grid), dim3(kBlock), 0, stream, a, split_col, split_w, split_l,
+                       split_big);
+    hipLaunchKernelGGL(k_split_big, dim3(fill_grid), dim3(kBlock), 0, stream, a, split_col, split_w, split_l,
+                       split_big);
   }
   if (timing) (void)hipEventRecord(t_timers.ev[1], stream);
 
@@ -1696,6 +1918,11 @@ og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, cons
     }
   }
   if (pred_edge && !pred) return fail(OG_ERR_INVALID_ARG);
+  if (s->flags & OG_FLAG_LIGHT_HEAVY) {
+    if constexpr (std::is_same<W, IntW>::value)
+      return run<SplitW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
+    return fail(OG_ERR_INVALID_ARG);  // int32 weights only
+  }
   return run<W>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
 }
 
@@ -1714,6 +1941,7 @@ const char* og_status_string(og_status s) {
     case OG_ERR_WORKSPACE: return "workspace too small or a queue overflowed";
     case OG_ERR_HIP: return "HIP runtime error";
     case OG_ERR_ROUND_LIMIT: return "round limit reached";
+    case OG_ERR_INTERNAL: return "internal consistency check failed";
     default: return "unknown status";
   }
 }
@@ -1846,9 +2074,11 @@ og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const
 }
 
 size_t og_workspace_bytes_kcore(const og_graph* g, const og_schedule* s) {
-  if (!og::graph_ok(g, false) || !og::schedule_ok(s)) return 0;
+  if (!s) return 0;
   og_schedule r = og::resolved(s);
   r.delta = 1;
+  r.flags &= ~OG_FLAG_LIGHT_HEAVY;
+  if (!og::graph_ok(g, false) || !og::schedule_ok(&r)) return 0;
   return og::ws_bytes_for(g, &r, og::Shape{1, g->n, false, true});
 }
 
@@ -1859,12 +2089,14 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
     if (stats) stats->status = st;
     return st;
   };
-  if (!og::graph_ok(g, false) || !og::schedule_ok(s) || !core || !ws) return fail(OG_ERR_INVALID_ARG);
+  if (!s) return fail(OG_ERR_INVALID_ARG);
+  og_schedule r = *s;
+  r.delta = 1;  // one bucket per degree value: peeling needs the strict order
+  r.flags &= ~OG_FLAG_LIGHT_HEAVY;
+  if (!og::graph_ok(g, false) || !og::schedule_ok(&r) || !core || !ws) return fail(OG_ERR_INVALID_ARG);
   if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
   const og::Shape sh{1, g->n, false, true};
   if (!og::shape_ok(g, sh)) return fail(OG_ERR_INVALID_ARG);
-  og_schedule r = *s;
-  r.delta = 1;  // one bucket per degree value: peeling needs the strict order
   return og::run<og::CoreW>(g, sh, {}, {}, nullptr, &r, core, nullptr, nullptr, ws, ws_bytes, stats, stream, false);
 }
 

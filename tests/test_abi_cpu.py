@@ -47,6 +47,7 @@ def test_version_and_strings():
     assert og.version() >> 16 == 1
     assert og.status_string(0) == "ok"
     assert "workspace" in og.status_string(og.OG_ERR_WORKSPACE)
+    assert "internal" in og.status_string(og.OG_ERR_INTERNAL)
     assert og.status_string(12345) == "unknown status"
 
 
@@ -80,6 +81,15 @@ def test_workspace_bytes():
     base = (base + 255) // 256 * 256
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s2)) == base + vec
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s3)) == base + 3 * vec
+    # light/heavy split: + split copy of col and w, light counts, long-row
+    # list, bucket stamps and two heavy lists of (v, 0) entries
+    s4 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, flags=og.OG_FLAG_LIGHT_HEAVY).to_c()
+    evec = (g.m * 4 + 255) // 256 * 256
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s4)) == (65536 + 256 + 12 * 5000 * 8 + 2 * evec
+                                                                         + 3 * vec + 4 * vec)
+    lazy_split = og.Schedule(delta=4, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_LIGHT_HEAVY).to_c()
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(lazy_split)) == 0
+    assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s4)) == base + vec
     bad = og.Schedule(delta=0).to_c()
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(bad)) == 0
     g0 = _lib.OgGraph(0, 0, 0x1000, None, None)
@@ -88,7 +98,7 @@ def test_workspace_bytes():
 
 @pytest.mark.parametrize("field,value", [
     ("delta", 0), ("update", 3), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
-    ("max_rounds", -1), ("flags", 8), ("fusion_threshold", -2),
+    ("max_rounds", -1), ("flags", 16), ("fusion_threshold", -2),
 ])
 def test_invalid_schedule_rejected(field, value):
     lib = _lib.load()
