@@ -110,7 +110,15 @@ def workload_rmat(args) -> int:
             ("sssp_fused", None, og.sssp, og.Schedule(delta=args.rmat_delta, flags=og.OG_FLAG_TIMING)),
             ("sssp_lazy", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
                                                      flags=og.OG_FLAG_TIMING)),
-            ("wbfs", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING))):
+            ("sssp_split", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_EAGER_NO_FUSION,
+                                                      flags=og.OG_FLAG_TIMING | og.OG_FLAG_LIGHT_HEAVY)),
+            ("sssp_split_4delta", None, og.sssp, og.Schedule(delta=4 * args.rmat_delta, update=og.OG_EAGER_NO_FUSION,
+                                                             flags=og.OG_FLAG_TIMING | og.OG_FLAG_LIGHT_HEAVY)),
+            ("sssp_split_fused", None, og.sssp, og.Schedule(delta=args.rmat_delta,
+                                                            flags=og.OG_FLAG_TIMING | og.OG_FLAG_LIGHT_HEAVY)),
+            ("wbfs", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING)),
+            ("wbfs_split", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING
+                                                                 | og.OG_FLAG_LIGHT_HEAVY))):
         gx = dg if graph_w is None else og.DeviceGraph(dg.row_ptr, dg.col, torch.from_numpy(
             np.ascontiguousarray(graph_w, dtype=np.int32)).to(dev))
         fn(gx, srcs[0], sched, ws=ws)  # warm-up
