@@ -38,9 +38,19 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_road4096_traffic.txt
 ENGINE_SRC = os.path.join(ROOT, "paper_1911_07260_amd", "csrc", "og_engine.hip")
 
 
-def engine_hash() -> str:
-    with open(ENGINE_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+_GAPS = re.compile(r'(?:\s|//[^\n]*|/\*.*?\*/)+|"(?:\\.|[^"\\])*"', re.S)
+
+
+def engine_hash(text: str | None = None) -> str:
+    """First 16 hex digits of the SHA-256 of the engine source with every
+    run of comments and white space outside string literals made one blank,
+    so that counters recorded for a kernel stay attached to it through edits
+    of its comments and go stale with any change of its code."""
+    if text is None:
+        with open(ENGINE_SRC) as f:
+            text = f.read()
+    code = _GAPS.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", text).strip()
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def read_traffic(delta: int):
@@ -50,7 +60,7 @@ def read_traffic(delta: int):
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
-    h = re.search(r"engine_sha256_16:\s*(\w+)", text)
+    h = re.search(r"engine_code_sha256_16:\s*(\w+)", text)
     d = re.search(r"delta:\s*(\d+)", text)
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not (h and d and b) or h.group(1) != engine_hash() or int(d.group(1)) != delta:

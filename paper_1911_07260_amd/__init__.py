@@ -9,6 +9,16 @@ kernels.  Functions mirror the C ABI:
     ppsp(graph, src, dst, schedule)   og_ppsp
     astar(graph, src, dst, h, sched)  og_astar
     kcore(graph, schedule)            og_kcore  (coreness of every vertex)
+    sssp_batch / ppsp_batch / astar_batch
+                                      og_*_batch (many queries, one launch)
+    sssp_multi(graph, srcs, schedule) og_sssp_multi (several sources at 0)
+
+The Schedule selects the update mode (eager with or without bucket fusion,
+lazy), the engine (persistent kernel, one launch per round, or rounds
+replayed from a captured hipGraph) and flags (structure validation, light /
+heavy edge split).  ``diff`` holds the FP32 forward and backward passes
+(og_sssp_f32, og_sssp_backward_f32) and an autograd Function over them;
+``autotune`` searches Delta and the fusion threshold on the device.
 
 Each shortest-path call returns ``(dist, pred, stats)`` with int32 device
 tensors (pred is None when not requested) and a dict of counters.

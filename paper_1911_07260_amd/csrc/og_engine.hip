@@ -30,6 +30,26 @@
 // disjoint graphs stored as one block-diagonal CSR.  All queries share the
 // bucket sequence, so they advance together through the same rounds.
 //
+// The same round structure carries the other schedules and algorithms, each
+// as its own template instantiation so that adding one leaves the machine
+// code of the others unchanged:
+//   - IntW: integer distances (SSSP, wBFS with Delta = 1, PPSP with its
+//     early exit, A* with the estimate added to the bucket key).
+//   - FloatW: FP32 distances for the differentiable pass; the bucket of a
+//     float key is floor(d / Delta) on the float value.
+//   - CoreW: k-core (section 6.1) with the degree as priority and Delta = 1;
+//     peeling a vertex lowers its neighbours' degrees, clamped at the core
+//     value being peeled.
+//   - SplitW: integer distances with light and heavy edges kept apart; light
+//     edges are relaxed in the ordinary rounds, heavy edges once per finished
+//     bucket.
+//   - Lazy update (section 3.1; its schedules in section 5.1): changed
+//     vertices are collected once per round, with a flag to drop
+//     duplicates, and filed by their final priority after a second
+//     device-wide barrier.
+// Rounds run inside one persistent cooperative kernel, or one launch per
+// round from the host, or as rounds replayed from a captured hipGraph.
+//
 // Correctness does not depend on the cache coherence of plain loads of
 // dist: dist only decreases during a call, a plain load returns some past
 // value (>= the current one), and every decision that matters is taken on

@@ -9,14 +9,24 @@ import bench
 
 def test_traffic_matches_engine_and_delta(tmp_path, monkeypatch):
     f = tmp_path / "traffic.txt"
-    f.write_text("traffic_bytes_per_launch: 12345\ndelta: 512\nengine_sha256_16: " + bench.engine_hash() + "\n")
+    f.write_text("traffic_bytes_per_launch: 12345\ndelta: 512\nengine_code_sha256_16: " + bench.engine_hash() + "\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.read_traffic(512) == 12345.0
     assert bench.read_traffic(1024) is None
-    f.write_text("traffic_bytes_per_launch: 12345\ndelta: 512\nengine_sha256_16: 0000000000000000\n")
+    f.write_text("traffic_bytes_per_launch: 12345\ndelta: 512\nengine_code_sha256_16: 0000000000000000\n")
     assert bench.read_traffic(512) is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
     assert bench.read_traffic(512) is None
+
+
+def test_engine_hash_ignores_comments_only():
+    src = 'int a; // note\n  int  b; /* block\n note */ f("x  // y");\n'
+    h = bench.engine_hash(src)
+    assert bench.engine_hash('int a; int b; f("x  // y");') == h
+    assert bench.engine_hash('int a;\n/* other words */ int b; f("x  // y"); // tail') == h
+    assert bench.engine_hash('int a; int c; f("x  // y");') != h
+    assert bench.engine_hash('int a; int b; f("x // y");') != h
+    assert bench.engine_hash('int a; intb; f("x  // y");') != h
 
 
 def test_committed_profile_is_current():
