@@ -120,6 +120,10 @@ def workload_rmat(args) -> int:
             ("sssp_fused", None, og.sssp, og.Schedule(delta=args.rmat_delta, flags=og.OG_FLAG_TIMING)),
             ("sssp_lazy", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
                                                      flags=og.OG_FLAG_TIMING)),
+            ("sssp_lazy_pull", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
+                                                          flags=og.OG_FLAG_TIMING | og.OG_FLAG_DENSE_PULL)),
+            ("sssp_lazy_hybrid", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
+                                                            flags=og.OG_FLAG_TIMING | og.OG_FLAG_HYBRID_DIRECTION)),
             ("sssp_split", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_EAGER_NO_FUSION,
                                                       flags=og.OG_FLAG_TIMING | og.OG_FLAG_LIGHT_HEAVY)),
             ("sssp_split_4delta", None, og.sssp, og.Schedule(delta=4 * args.rmat_delta, update=og.OG_EAGER_NO_FUSION,
@@ -128,7 +132,13 @@ def workload_rmat(args) -> int:
                                                             flags=og.OG_FLAG_TIMING | og.OG_FLAG_LIGHT_HEAVY)),
             ("wbfs", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING)),
             ("wbfs_split", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING
-                                                                 | og.OG_FLAG_LIGHT_HEAVY))):
+                                                                 | og.OG_FLAG_LIGHT_HEAVY)),
+            ("wbfs_lazy", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, update=og.OG_LAZY_UPDATE,
+                                                                flags=og.OG_FLAG_TIMING)),
+            ("wbfs_lazy_pull", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, update=og.OG_LAZY_UPDATE,
+                                                                     flags=og.OG_FLAG_TIMING | og.OG_FLAG_DENSE_PULL)),
+            ("wbfs_lazy_hybrid", (g.w % 23) + 1, og.wbfs, og.Schedule(
+                delta=1, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_TIMING | og.OG_FLAG_HYBRID_DIRECTION))):
         gx = dg if graph_w is None else og.DeviceGraph(dg.row_ptr, dg.col, torch.from_numpy(
             np.ascontiguousarray(graph_w, dtype=np.int32)).to(dev))
         fn(gx, srcs[0], sched, ws=ws)  # warm-up
@@ -141,7 +151,7 @@ def workload_rmat(args) -> int:
         out[name] = {"ms_per_query": round(ms, 3), "gteps": round(e / (ms * 1e-3) / 1e9, 4),
                      "engine_ms": round(float(np.mean([x["engine_ms"] for x in sts])), 3),
                      "relaxations": int(np.mean([x["relaxations"] for x in sts])), "rounds": int(np.mean(
-                         [x["rounds"] for x in sts]))}
+                         [x["rounds"] for x in sts])), "barriers": int(np.mean([x["barriers"] for x in sts]))}
         print(f"[bench] rmat {name}: {ms:.2f} ms/query", file=sys.stderr, flush=True)
     parity = None
     if not args.no_cpu:
@@ -339,8 +349,9 @@ def workload_kcore(args) -> int:
     import paper_1911_07260_amd as og
     dev = torch.device("cuda:0")
     res = {}
-    modes = (("lazy", og.OG_LAZY_UPDATE), ("eager", og.OG_EAGER_NO_FUSION),
-             ("eager_fused", og.OG_EAGER_WITH_FUSION))
+    modes = (("lazy", og.OG_LAZY_UPDATE, 0), ("eager", og.OG_EAGER_NO_FUSION, 0),
+             ("eager_fused", og.OG_EAGER_WITH_FUSION, 0), ("lazy_pull", og.OG_LAZY_UPDATE, og.OG_FLAG_DENSE_PULL),
+             ("lazy_hybrid", og.OG_LAZY_UPDATE, og.OG_FLAG_HYBRID_DIRECTION))
 
     def certificate(dg, core):
         src = torch.repeat_interleave(torch.arange(dg.n, device=dev),
@@ -359,8 +370,8 @@ def workload_kcore(args) -> int:
         del g
         ws = og.Workspace(dev)
         out = {"n": dg.n, "m": dg.m}
-        for mname, upd in modes:
-            sched = og.Schedule(update=upd, window_buckets=64, flags=og.OG_FLAG_TIMING)
+        for mname, upd, fl in modes:
+            sched = og.Schedule(update=upd, window_buckets=64, flags=og.OG_FLAG_TIMING | fl)
             og.kcore(dg, sched, ws=ws)  # warm-up
             torch.cuda.synchronize()
             reps = 3
@@ -385,14 +396,16 @@ def workload_kcore(args) -> int:
         want = oracle.get().kcore(g)
         cpu_s = time.perf_counter() - t
         dg = og.DeviceGraph.from_host(g, dev, weights=False)
-        parity = all(np.array_equal(og.kcore(dg, og.Schedule(update=u))[0].cpu().numpy(), want) for _, u in modes)
+        parity = all(np.array_equal(og.kcore(dg, og.Schedule(update=u, flags=fl))[0].cpu().numpy(), want)
+                     for _, u, fl in modes)
         cpu = {"value": round(cpu_s * 1e3, 3), "unit": "ms", "cores": 1, "kind": "oracle",
                "sample": f"R-MAT scale 18 (n={g.n}, m={g.m}), minimum-degree peeling with a binary heap",
                "parity_all_modes": parity}
     r = res[f"rmat{args.scale}"]
     print(_line("ms per k-core decomposition, R-MAT", r["lazy"]["ms"], "ms", 3, 1, r["lazy"]["ms"],
                 {"workload": f"k-core of R-MAT scale {args.scale} (edge factor 16, symmetric) and road-like "
-                             "4096^2; lazy constant-sum vs eager updates, 64 window buckets"},
+                             "4096^2; lazy constant-sum (push, dense pull, hybrid direction) vs eager updates, "
+                             "64 window buckets"},
                 higher_is_better=False, results=res, cpu_baseline=cpu), flush=True)
     return 0
 

@@ -85,6 +85,31 @@ typedef int32_t og_status;
                                updates only (og_sssp_f32 and a lazy schedule
                                return OG_ERR_INVALID_ARG); the workspace holds
                                a split copy of the rows.  og_kcore ignores it. */
+#define OG_FLAG_DENSE_PULL 16u /* traversal direction DensePull (section 4.2,
+                               configApplyDirection; combined with lazy updates
+                               as in section 5.1): every round first marks its
+                               frontier in a dense per-vertex array, then each
+                               vertex that can still improve reads its own row
+                               as its in-edges and takes the best offer of the
+                               marked neighbours, with no atomic operation on
+                               the destination.  Requires OG_LAZY_UPDATE and a
+                               SYMMETRIC graph (each edge (u, v, w) has a
+                               reverse (v, u, w); with OG_FLAG_VALIDATE this is
+                               checked, by a 64-bit hash of the edge multiset,
+                               and a failure returns OG_ERR_INVALID_ARG).
+                               int32 weights (og_sssp_f32 returns
+                               OG_ERR_INVALID_ARG).  Applies to og_kcore too
+                               (a vertex counts its peeled neighbours).  The
+                               workspace holds the frontier marks (8 bytes
+                               per vertex; og_kcore: one bit) and a list of
+                               slices of the rows longer than 8192 edges.    */
+#define OG_FLAG_HYBRID_DIRECTION 32u /* SparsePush-DensePull: as
+                               OG_FLAG_DENSE_PULL, but a round pulls only when
+                               its input holds more than n/20 entries (the
+                               frontier's edges, estimated as its size times the
+                               mean degree, exceed m/20) and pushes otherwise.
+                               Same requirements; not together with
+                               OG_FLAG_DENSE_PULL.                            */
 
 /* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
 #define OG_EAGER_NO_FUSION 0

@@ -25,6 +25,8 @@ OG_FLAG_VALIDATE = 1
 OG_FLAG_ASYNC = 2
 OG_FLAG_TIMING = 4
 OG_FLAG_LIGHT_HEAVY = 8
+OG_FLAG_DENSE_PULL = 16
+OG_FLAG_HYBRID_DIRECTION = 32
 
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1

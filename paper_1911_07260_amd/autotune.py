@@ -8,7 +8,9 @@ library's HIP events (`OG_FLAG_TIMING`, bucket-engine time only); the search
 is
 
   1. Delta on a coarse power-of-two ladder around the weight scale, with
-     and without bucket fusion (the two update strategies of section 4.2);
+     and without bucket fusion (the two eager update strategies of section
+     4.2), and optionally the lazy update pushing or with the
+     SparsePush-DensePull hybrid direction (section 4.2; symmetric graphs);
   2. the fusion threshold and the window size around the best candidate;
   3. Delta refined by factors of sqrt(2) around the best value;
   4. the workgroup count.
@@ -27,8 +29,10 @@ from dataclasses import asdict, dataclass, field
 import numpy as np
 import torch
 
-from . import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_TIMING, DeviceGraph, Schedule, Workspace, astar_batch,
-               ppsp_batch, sssp, sssp_batch)
+from . import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_TIMING,
+               OG_LAZY_UPDATE, DeviceGraph, Schedule, Workspace, astar_batch, ppsp_batch, sssp, sssp_batch)
+
+_DIRECTIONS = OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION
 
 
 @dataclass
@@ -130,15 +134,20 @@ class Autotuner:
         scored.sort(key=lambda x: (x[0], x[1]))
         return scored[0][2], scored[0][0]
 
-    def tune(self, weight_scale: float, hop_weight: float | None = None) -> TuneResult:
+    def tune(self, weight_scale: float, hop_weight: float | None = None, lazy: bool = False) -> TuneResult:
         """weight_scale: a typical edge weight (e.g. the median); the Delta
-        ladder spans weight_scale/16 .. weight_scale*1024."""
+        ladder spans weight_scale/16 .. weight_scale*1024.  lazy: also try
+        the lazy update, pushing and with the hybrid direction (the graph
+        must then be symmetric)."""
         t0 = time.perf_counter()
         base = self.base
         lo = max(1, int(weight_scale / 16))
         deltas = sorted({1 << k for k in range(max(0, int(math.log2(lo))), int(math.log2(weight_scale * 1024)) + 1)})
-        cands = [Schedule(**{**asdict(base), "delta": d, "update": u})
-                 for d in deltas for u in (OG_EAGER_WITH_FUSION, OG_EAGER_NO_FUSION)]
+        modes = [(OG_EAGER_WITH_FUSION, 0), (OG_EAGER_NO_FUSION, 0)]
+        if lazy:
+            modes += [(OG_LAZY_UPDATE, 0), (OG_LAZY_UPDATE, OG_FLAG_HYBRID_DIRECTION)]
+        cands = [Schedule(**{**asdict(base), "delta": d, "update": u, "flags": (base.flags & ~_DIRECTIONS) | fl})
+                 for d in deltas for u, fl in modes]
         best, best_ms = self._best(cands)
         # threshold / window around the best
         cands = [best]
@@ -153,5 +162,5 @@ class Autotuner:
         # workgroups
         cands = [best] + [Schedule(**{**asdict(best), "workgroups": w}) for w in (256, 512, 1024)]
         best, best_ms = self._best(cands)
-        best = Schedule(**{**asdict(best), "flags": base.flags})
+        best = Schedule(**{**asdict(best), "flags": (base.flags & ~_DIRECTIONS) | (best.flags & _DIRECTIONS)})
         return TuneResult(best=best, best_ms=best_ms, trials=list(self.trials), seconds=time.perf_counter() - t0)

@@ -10,6 +10,7 @@
 //   og_bench [--graph road|rmat] [--side 4096] [--scale 24] [--delta 512]
 //            [--steps 8] [--warmup 2] [--update fused|unfused|lazy]
 //            [--engine persistent|host|graph] [--window K] [--kcore]
+//            [--direction push|pull|hybrid]   (pull and hybrid need --update lazy)
 //            [--copy-calibration]
 //
 // --copy-calibration instead runs a plain copy kernel over 1 GiB three
@@ -75,6 +76,7 @@ int main(int argc, char** argv) {
   int side = 4096, scale = 24, delta = 512, steps = 8, warmup = 2, nsrc = 8, window = 0;
   int update = OG_EAGER_WITH_FUSION, engine = OG_ENGINE_PERSISTENT;
   bool rmat = false, kcore = false;
+  uint32_t direction = 0;
   for (int i = 1; i < argc; ++i) {
     auto next = [&](void) -> const char* {
       if (i + 1 >= argc) { std::fprintf(stderr, "missing value for %s\n", argv[i]); std::exit(2); }
@@ -98,6 +100,10 @@ int main(int argc, char** argv) {
       engine = !std::strcmp(e, "host") ? OG_ENGINE_HOST_ROUNDS
                : !std::strcmp(e, "graph") ? OG_ENGINE_GRAPH_ROUNDS
                                           : OG_ENGINE_PERSISTENT;
+    }
+    else if (!std::strcmp(argv[i], "--direction")) {
+      const char* d = next();
+      direction = !std::strcmp(d, "pull") ? OG_FLAG_DENSE_PULL : !std::strcmp(d, "hybrid") ? OG_FLAG_HYBRID_DIRECTION : 0u;
     }
     else if (!std::strcmp(argv[i], "--copy-calibration")) return copy_calibration();
     else { std::fprintf(stderr, "unknown argument %s\n", argv[i]); return 2; }
@@ -138,7 +144,7 @@ int main(int argc, char** argv) {
   s.delta = delta;
   s.update = update;
   s.engine = engine;
-  s.flags = OG_FLAG_TIMING;
+  s.flags = OG_FLAG_TIMING | direction;
   if (window > 0) s.window_buckets = window;
   const size_t wsb = kcore ? og_workspace_bytes_kcore(&g, &s) : og_workspace_bytes(&g, &s);
   void* ws = nullptr;
@@ -165,9 +171,9 @@ int main(int argc, char** argv) {
     }
   }
   std::printf("{\"graph\": \"%s\", \"call\": \"%s\", \"n\": %d, \"m\": %lld, \"delta\": %d, \"update\": %d, "
-              "\"engine\": %d, \"steps\": %d, \"engine_ms\": %.4f, \"pred_ms\": %.4f, \"rounds\": %.1f, "
+              "\"engine\": %d, \"direction\": %u, \"steps\": %d, \"engine_ms\": %.4f, \"pred_ms\": %.4f, \"rounds\": %.1f, "
               "\"reached_edges\": %.0f}\n",
-              rmat ? "rmat" : "road", kcore ? "og_kcore" : "og_sssp", n, (long long)m, delta, update, engine, steps,
+              rmat ? "rmat" : "road", kcore ? "og_kcore" : "og_sssp", n, (long long)m, delta, update, engine, direction, steps,
               eng / steps, pred / steps, rounds / steps, tot_e / steps);
   CHECK(hipStreamDestroy(stream));
   CHECK(hipFree(ws));

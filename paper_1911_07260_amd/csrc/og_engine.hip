@@ -87,6 +87,20 @@ constexpr int kInf = INT_MAX;
 constexpr int kPeeled = INT_MAX;  // k-core mark of a peeled vertex (above every generation)
 
 enum : int { kInWin = 0, kInSpill = 1, kInFar = 2, kInHeavy = 3 };
+// Direction of the rounds of a pull instantiation.  The hybrid pulls when
+// the round input holds more than n / kPullDiv entries: the frontier's edges
+// estimated as its size times the mean degree, against m / kPullDiv.
+enum : int { kPullNever = 0, kPullAlways = 1, kPullHybrid = 2 };
+constexpr unsigned kPullDiv = 20;
+// A pull round expands rows of up to kLongRow edges inside 256-vertex
+// batches; longer rows are cut into slices of kSlice edges that are handed
+// out to workgroups like the batches.  Slices per graph are at most
+// m / kSlice + m / kLongRow + 1.
+constexpr int kLongRow = 8192;
+constexpr int kSlice = 2048;
+__host__ __device__ inline unsigned long long slice_cap(long long m) {
+  return (unsigned long long)(m / kSlice + m / kLongRow + 1);
+}
 // Light/heavy split: LDS ring entries carry a vertex's light-edge count with
 // this bit set when the vertex also has heavy edges.
 constexpr int kHeavyBit = 1 << 30;
@@ -119,6 +133,7 @@ struct alignas(128) Control {
   unsigned far_gen;  // generation of the pending far list (k-core filing)
   unsigned hout;     // light/heavy split: heavy list receiving settled vertices
   unsigned hgen;     // light/heavy split: generation of that list (heavy rounds so far)
+  unsigned pull;     // direction of this round: 1 = dense pull (pull instantiations)
 };
 
 // Device-side control block at the start of the workspace.
@@ -139,6 +154,8 @@ struct Ctl {
   Word64 st[kStCount];
   Word heavy_tail[2];  // light/heavy split: settled vertices per heavy list
   Word big_rows;       // light/heavy split: rows left to the wavefront split pass
+  Word64 sym;          // symmetry checksum of OG_FLAG_VALIDATE with a pull direction
+  Word slices;         // pull direction: row slices listed per copy of the graph
 };
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block too large");
 
@@ -180,6 +197,10 @@ struct Args {
   int2* heavy;        // 2 lists of hcap (v, 0) entries: vertices settled in a bucket
   unsigned hcap;
   long long m;
+  int pull;          // direction: kPullNever, kPullAlways or kPullHybrid
+  int2* front;       // [n] pull, SSSP: (round stamp, distance) of the round's frontier vertices
+  unsigned* fbits;   // [ceil(n / 32)] pull, k-core: bitmap of the vertices peeled in the round
+  const int2* slices;  // pull: (base vertex, slice index) of every long row's slices
 };
 
 struct Counters {
@@ -206,6 +227,7 @@ struct Smem {
   int in_kind, in_index, done, spill_out, far_out;
   int hout;       // light/heavy split
   unsigned hgen;  // light/heavy split
+  int pull;       // this round pulls
 };
 
 // ------------------------------------------------- device-coherent access
@@ -255,6 +277,8 @@ __device__ __forceinline__ void set_status(Ctl* c, int st) {
 struct IntW {
   static constexpr int kInfBits = INT_MAX;
   static constexpr bool kSplit = false;
+  static constexpr bool kCore = false;
+  static constexpr bool kPull = false;
   // nd = d + w; false (and a status) for a negative weight or a sum that
   // reaches INT32_MAX
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
@@ -283,6 +307,8 @@ struct IntW {
 struct FloatW {
   static constexpr int kInfBits = 0x7f800000;  // +inf
   static constexpr bool kSplit = false;
+  static constexpr bool kCore = false;
+  static constexpr bool kPull = false;
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
     const float w = __int_as_float(wraw);
     if (!(w >= 0.0f) || w == __int_as_float(kInfBits)) {  // negative, NaN or infinite
@@ -311,7 +337,9 @@ struct FloatW {
 
 // k-core: the priority of a vertex is its remaining degree (the "dist"
 // array is the priority vector), one bucket per value; no weights.
-struct CoreW : IntW {};
+struct CoreW : IntW {
+  static constexpr bool kCore = true;
+};
 
 // Light/heavy split (Meyer and Sanders' Delta-stepping; the paper relaxes
 // every edge): int32 distances, rounds relax the light edges (w < Delta)
@@ -321,6 +349,20 @@ struct CoreW : IntW {};
 struct SplitW : IntW {
   static constexpr bool kSplit = true;
   __device__ static bool light(const Args& a, int wraw) { return wraw < (int)a.delta; }
+};
+
+// Direction optimisation with lazy updates (section 4.2, DensePull and the
+// SparsePush-DensePull hybrid; section 5.1: no atomics on the destination).
+// A pull round first marks its frontier in a dense per-vertex array; after a
+// device-wide barrier every vertex that can still improve reads its own row
+// as its in-edges (the graph is symmetric) and takes the best value offered
+// by marked neighbours.  Separate instantiations of the int32 and k-core
+// engines.
+struct PullW : IntW {
+  static constexpr bool kPull = true;
+};
+struct CorePullW : CoreW {
+  static constexpr bool kPull = true;
 };
 
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
@@ -734,6 +776,13 @@ __device__ void process_batch_core(const Args& a, Smem& s, Counters& c, int4 ent
 // peeled neighbours counted in the round, clamped at the current level.
 template <class W>
 __device__ void run_flush(const Args& a, Smem& s, Counters& c) {
+  if constexpr (W::kPull && W::kCore) {
+    if (s.pull) {  // the pull phase is over: clear the bitmap of peeled vertices
+      const unsigned words = ((unsigned)a.n + 31u) / 32u;
+      for (unsigned i = blockIdx.x * (unsigned)kBlock + threadIdx.x; i < words; i += (unsigned)a.nwg * kBlock)
+        st_dev(a.fbits + i, 0u);
+    }
+  }
   const unsigned cnt0 = ld_dev(&a.ctl->buf_tail.v);
   const unsigned cnt = cnt0 < a.buf_cap ? cnt0 : a.buf_cap;
   const unsigned cur = s.cur;
@@ -744,7 +793,7 @@ __device__ void run_flush(const Args& a, Smem& s, Counters& c) {
     unsigned b = 0;
     if (i < cnt) {
       u = (int)ld_dev(reinterpret_cast<const unsigned*>(a.buf) + i);
-      if constexpr (std::is_same<W, CoreW>::value) {
+      if constexpr (W::kCore) {
         const int k = atomicExch(&a.aux[u], 0);
         const int now = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + u);
         if (now > (int)cur) {
@@ -761,7 +810,7 @@ __device__ void run_flush(const Args& a, Smem& s, Counters& c) {
         has = true;
       }
     }
-    if constexpr (std::is_same<W, CoreW>::value) {
+    if constexpr (W::kCore) {
       route_core(a, s, c, has, u, d, 0, 0);
     } else {
       int tgt = 0;
@@ -869,10 +918,290 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
         ent = make_int4(e.x, e.y, 0, 0);
       }
     }
-    if constexpr (std::is_same<W, CoreW>::value) process_batch_core(a, s, c, ent, mode == 1);
+    if constexpr (W::kCore) process_batch_core(a, s, c, ent, mode == 1);
     else process_batch<W>(a, s, c, ent, mode == 1);
     c.batches++;
     c.round_batches++;
+  }
+}
+
+// Direction of a round whose input holds `count` entries (1 = pull).
+__device__ __forceinline__ unsigned pull_round(const Args& a, unsigned count) {
+  return a.pull == kPullAlways || (a.pull == kPullHybrid && count > (unsigned)a.n / kPullDiv) ? 1u : 0u;
+}
+
+// Frontier of a pull round, written in the mark phase and read with one
+// device-scope load per edge in the pull phase.  SSSP: (round stamp,
+// distance) per vertex; stamps are unique within a call, so nothing is
+// cleared between rounds.  k-core needs membership only: a bitmap (n / 8
+// bytes), cleared in the filing phase of each pull round.
+__device__ __forceinline__ int pull_stamp(const Smem& s) { return (int)s.round + 1; }
+__device__ __forceinline__ void mark_peeled(const Args& a, int v) {
+  atomicOr(&a.fbits[(unsigned)v >> 5], 1u << ((unsigned)v & 31u));
+}
+
+// First phase of a pull round: the live entries of the round input (entry
+// distance equal to the vertex's current one, bucket not later than the
+// current one) are marked in the frontier array with the round's stamp and
+// their distance; an entry of a later bucket (a far round) is filed there;
+// stale entries are dropped.  k-core: a live entry is a vertex not yet
+// peeled whose degree equals the current level; it is peeled here and set
+// in the bitmap.
+template <class W>
+__device__ void run_mark(const Args& a, Smem& s, Counters& c) {
+  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const unsigned count = s.in_count;
+  const unsigned cur = s.cur;
+  const int stamp = pull_stamp(s);
+  for (unsigned base = blockIdx.x * (unsigned)kBlock; base < count; base += (unsigned)a.nwg * kBlock) {
+    const unsigned i = base + threadIdx.x;
+    bool later = false;
+    int v = 0, d = 0;
+    unsigned rb = 0;
+    if (i < count) {
+      const int2 e = ld_entry(in, i);
+      v = e.x;
+      d = e.y;
+      const int now = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + v);
+      if constexpr (W::kCore) {
+        if ((int)ld_dev(reinterpret_cast<const unsigned*>(a.mark) + v) != kPeeled) {
+          if ((unsigned)now == cur) {
+            if (atomicExch(&a.mark[v], kPeeled) != kPeeled) mark_peeled(a, v);
+          } else if ((unsigned)now > cur) {
+            later = true;
+            d = now;
+          }
+        }
+      } else if (d == now) {
+        rb = W::bucket(a, W::key(a, v, d));
+        if (rb > cur) later = true;
+        else st_entry(a.front, (size_t)v, stamp, d);
+      }
+    }
+    if constexpr (W::kCore) {
+      route_core(a, s, c, later, v, d, 0, 0);
+    } else {
+      int tgt = 0;
+      if (later) tgt = rb < s.win_hi ? (int)(rb & (unsigned)(a.K - 1)) : a.K + 1;
+      wave_push_global(a, s, c, later, tgt, v, d, rb);
+    }
+  }
+}
+
+// Whether vertex v (current value dv) can still improve in a pull round.
+// SSSP: every frontier distance is at least cur * Delta, so a vertex at or
+// below it cannot (not so with an A* estimate in the bucket key).  k-core:
+// a vertex not peeled whose degree is above the current level.
+template <class W>
+__device__ __forceinline__ bool pull_open(const Args& a, unsigned cur, int v, int dv) {
+  if constexpr (W::kCore) {
+    return dv > (int)cur && (int)ld_dev(reinterpret_cast<const unsigned*>(a.mark) + v) != kPeeled;
+  } else {
+    const unsigned long long lo = a.h ? 0ull : (unsigned long long)cur * a.delta;
+    return (unsigned long long)(unsigned)dv > lo;
+  }
+}
+
+// Up to kPullIlp edges of a pull round per lane, their loads issued
+// together: the columns, then the neighbours' frontier entries, then the
+// weights of the frontier neighbours.  offer[k]: the best value edge k
+// brings (SSSP: the neighbour's marked distance plus the weight, kInf if
+// none; k-core: 1 for a peeled neighbour, else 0).
+constexpr int kPullIlp = 2;
+template <class W>
+__device__ __forceinline__ void pull_edges(const Args& a, Counters& c, int stamp, const int (&edge)[kPullIlp],
+                                           const int (&voff)[kPullIlp], const bool (&ok)[kPullIlp],
+                                           int (&offer)[kPullIlp]) {
+  int u[kPullIlp];
+#pragma unroll
+  for (int k = 0; k < kPullIlp; ++k) u[k] = ok[k] ? a.col[edge[k]] + voff[k] : 0;
+  int2 f[kPullIlp];
+#pragma unroll
+  for (int k = 0; k < kPullIlp; ++k) {
+    if constexpr (W::kCore)
+      f[k] = make_int2(ok[k] ? (int)((ld_dev(a.fbits + ((unsigned)u[k] >> 5)) >> ((unsigned)u[k] & 31u)) & 1u) : 0, 0);
+    else
+      f[k] = ok[k] ? ld_entry(a.front, (size_t)u[k]) : make_int2(0, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < kPullIlp; ++k) {
+    const bool hit = ok[k] && f[k].x == (W::kCore ? 1 : stamp);
+    offer[k] = W::kCore ? 0 : kInf;
+    if (hit) {
+      c.relax++;
+      if constexpr (W::kCore) {
+        offer[k] = 1;
+      } else {
+        int nd = 0;
+        if (W::add(a, f[k].y, a.w[edge[k]], &nd)) offer[k] = nd;
+      }
+    }
+  }
+}
+
+// Appends one vertex to the change buffer (a single lane).
+__device__ __forceinline__ void append_buf_one(const Args& a, int v) {
+  const unsigned pos = atomicAdd(&a.ctl->buf_tail.v, 1u);
+  if (pos < a.buf_cap) st_dev(reinterpret_cast<unsigned*>(a.buf) + pos, (unsigned)v);
+  else set_status(a.ctl, OG_ERR_WORKSPACE);
+}
+
+// A slice of up to kSlice edges of one long row, by the whole workgroup:
+// the offers are reduced over the workgroup and combined into the vertex
+// with one atomic (several slices share the row), the vertex recorded in
+// the change buffer by the first slice that changes it (the lazy flag).
+template <class W>
+__device__ void pull_slice(const Args& a, Smem& s, Counters& c, unsigned item) {
+  const int tid = threadIdx.x;
+  const unsigned cur = s.cur;
+  const unsigned per = ld_dev(&a.ctl->slices.v);  // > 0: item is a slice
+  const unsigned q = item / per;
+  const int2 sl = a.slices[item - q * per];
+  const int vb = sl.x;
+  const int v = (int)q * a.nbase + vb;
+  if (tid == 0) {
+    const int dv = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + v);
+    s.mode = pull_open<W>(a, cur, v, dv) ? 1 : 0;
+    s.nb = dv;
+  }
+  __syncthreads();
+  if (!s.mode) return;
+  const int dv = s.nb;
+  const long long r0 = a.row_ptr[vb] + (long long)sl.y * kSlice;
+  const long long rend = a.row_ptr[vb + 1];
+  const long long r1 = rend - r0 < kSlice ? rend : r0 + kSlice;
+  const int stamp = pull_stamp(s);
+  int best = W::kCore ? 0 : dv;
+  for (int k0 = 0; k0 < kSlice / kBlock; k0 += kPullIlp) {
+    int edge[kPullIlp], voff[kPullIlp], offer[kPullIlp];
+    bool ok[kPullIlp];
+#pragma unroll
+    for (int k = 0; k < kPullIlp; ++k) {
+      const long long e = r0 + (long long)(k0 + k) * kBlock + tid;
+      ok[k] = e < r1;
+      edge[k] = ok[k] ? (int)e : 0;
+      voff[k] = v - vb;
+    }
+    pull_edges<W>(a, c, stamp, edge, voff, ok, offer);
+#pragma unroll
+    for (int k = 0; k < kPullIlp; ++k) best = W::kCore ? best + offer[k] : (offer[k] < best ? offer[k] : best);
+  }
+  // workgroup reduction: sum (k-core) or minimum (SSSP)
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int y = __shfl_xor(best, o);
+    best = W::kCore ? best + y : (y < best ? y : best);
+  }
+  if (lane_id() == 0) s.wsum[tid / kWave] = best;
+  __syncthreads();
+  if (tid == 0) {
+    int r = s.wsum[0];
+    for (int i = 1; i < kWaves; ++i) r = W::kCore ? r + s.wsum[i] : (s.wsum[i] < r ? s.wsum[i] : r);
+    if constexpr (W::kCore) {
+      if (r > 0 && atomicAdd(&a.aux[v], r) == 0) append_buf_one(a, v);
+    } else if (r < dv) {
+      const int old = atomicMin(&a.dist[v], r);
+      if (r < old) {
+        c.improve++;
+        if (atomicExch(&a.aux[v], 1) == 0) append_buf_one(a, v);
+      }
+    }
+  }
+}
+
+// Second phase of a pull round.  Work items are handed out one at a time
+// through the chunk cursor: first the slices of the long rows (every copy
+// of the graph), then batches of kBlock vertices.  In a batch, a vertex
+// that can still improve and whose row has at most kLongRow edges has its
+// row expanded over the workgroup; the frontier neighbours' offers are
+// combined per vertex in LDS (minimum of distance + weight; k-core: the
+// number of peeled neighbours).  Only the vertex's own lane writes its
+// result, so the destination needs no atomic: a lowered distance is stored,
+// a k-core count is left for the filing phase, and the vertex is recorded
+// in the change buffer.
+template <class W>
+__device__ void run_pull(const Args& a, Smem& s, Counters& c) {
+  const int tid = threadIdx.x;
+  const unsigned cur = s.cur;
+  const unsigned nsl = ld_dev(&a.ctl->slices.v) * (unsigned)a.reps;  // at most slice_cap(m) per copy
+  const unsigned nvb = ((unsigned)a.n + kBlock - 1) / kBlock;
+  const int stamp = pull_stamp(s);
+  for (;;) {
+    __syncthreads();  // the previous item's shared state is no longer read
+    if (tid == 0) s.gbase = atomicAdd(&a.ctl->in_head.v, 1u);
+    __syncthreads();
+    const unsigned item = s.gbase;
+    if (item >= nsl + nvb) break;
+    c.batches++;
+    c.round_batches++;
+    if (item < nsl) {
+      pull_slice<W>(a, s, c, item);
+      continue;
+    }
+    const unsigned base = (item - nsl) * (unsigned)kBlock;
+    const int nb = (unsigned)a.n - base < (unsigned)kBlock ? (int)((unsigned)a.n - base) : kBlock;
+    const int v = (int)base + tid;
+    int deg = 0, start = 0, voff = 0, dv = 0;
+    if (tid < nb) {
+      const int vb = a.reps == 1 ? v : (int)((unsigned)v % (unsigned)a.nbase);
+      voff = v - vb;
+      dv = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + v);
+      const long long r0 = a.row_ptr[vb];
+      const int len = (int)(a.row_ptr[vb + 1] - r0);
+      if (len <= kLongRow && pull_open<W>(a, cur, v, dv)) {
+        start = (int)r0;
+        deg = len;
+      }
+    }
+    int total;
+    const int off = block_excl_scan(deg, s, &total);
+    s.boff[tid] = off;
+    s.bstart[tid] = start;
+    s.bvo[tid] = voff;
+    s.bd[tid] = W::kCore ? 0 : dv;
+    __syncthreads();
+    for (int eb = 0; eb < total; eb += kPullIlp * kBlock) {
+      int edge[kPullIlp], voff[kPullIlp], slot[kPullIlp], offer[kPullIlp];
+      bool ok[kPullIlp];
+#pragma unroll
+      for (int k = 0; k < kPullIlp; ++k) {
+        const int e = eb + k * kBlock + tid;
+        ok[k] = e < total;
+        int lo_i = 0, hi_i = nb - 1;
+        while (ok[k] && lo_i < hi_i) {
+          const int mid = (lo_i + hi_i + 1) >> 1;
+          if (s.boff[mid] <= e) lo_i = mid;
+          else hi_i = mid - 1;
+        }
+        slot[k] = lo_i;
+        edge[k] = ok[k] ? s.bstart[lo_i] + (e - s.boff[lo_i]) : 0;
+        voff[k] = s.bvo[lo_i];
+      }
+      pull_edges<W>(a, c, stamp, edge, voff, ok, offer);
+#pragma unroll
+      for (int k = 0; k < kPullIlp; ++k) {
+        if constexpr (W::kCore) {
+          if (offer[k]) atomicAdd(&s.bd[slot[k]], offer[k]);
+        } else {
+          if (offer[k] < s.bd[slot[k]]) atomicMin(&s.bd[slot[k]], offer[k]);
+        }
+      }
+    }
+    __syncthreads();
+    bool changed = false;
+    if (deg > 0) {
+      const int r = s.bd[tid];
+      if constexpr (W::kCore) {
+        if (r > 0) {
+          st_dev(reinterpret_cast<unsigned*>(a.aux) + v, (unsigned)r);
+          changed = true;
+        }
+      } else if (r < dv) {
+        st_dev(reinterpret_cast<unsigned*>(a.dist) + v, (unsigned)r);
+        c.improve++;
+        changed = true;
+      }
+    }
+    wave_append_buf(a, changed, v);
   }
 }
 
@@ -1023,6 +1352,7 @@ __device__ void decide(const Args& a) {
     if (nhout != hout) st_dev(&c->c.hgen, ld_dev(&c->c.hgen) + 1u);
     st_dev(&c->c.hout, nhout);
   }
+  if constexpr (W::kPull) st_dev(&c->c.pull, done ? 0u : pull_round(a, count));
   st_dev(&c->c.done, done);
   st_dev(&c->c.round, round);
 }
@@ -1045,6 +1375,7 @@ __device__ void load_control(const Args& a, Smem& s) {
     s.hout = (int)ld_dev(&c->c.hout);
     s.hgen = ld_dev(&c->c.hgen);
   }
+  if constexpr (W::kPull) s.pull = (int)ld_dev(&c->c.pull);
   s.done = ld_dev(&c->c.done) || ld_dev(&c->status.v) != 0;
 }
 
@@ -1259,6 +1590,31 @@ __global__ void k_init_ctl(Args a) {
   c->need.v = (unsigned)a.nsrc;
 }
 
+// Pull instantiations: the direction of the first round.
+__global__ void k_init_pull(Args a) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctl->c.pull = pull_round(a, a.ctl->c.in_count);
+}
+
+// Pull instantiations: the slices of every row longer than kLongRow, as
+// (vertex, slice index) pairs; the count goes to the control block.  The
+// list never exceeds slice_cap(m) entries (a longer one would mean a
+// malformed graph and ends the call with OG_ERR_INTERNAL).
+__global__ __launch_bounds__(kBlock) void k_pull_slices(Args a, int2* slices) {
+  const unsigned long long cap = slice_cap(a.m);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long vb = (long long)blockIdx.x * blockDim.x + threadIdx.x; vb < a.nbase; vb += stride) {
+    const long long deg = a.row_ptr[vb + 1] - a.row_ptr[vb];
+    if (deg <= kLongRow) continue;
+    const unsigned long long k = (unsigned long long)((deg + kSlice - 1) / kSlice);
+    const unsigned long long base = atomicAdd(&a.ctl->slices.v, (unsigned)k);
+    if (base + k > cap) {
+      set_status(a.ctl, OG_ERR_INTERNAL);
+      continue;
+    }
+    for (unsigned long long j = 0; j < k; ++j) slices[base + j] = make_int2((int)vb, (int)j);
+  }
+}
+
 __global__ void k_far_min_init(Ctl* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c->far_min[0].v = kNoBucket;
 }
@@ -1284,6 +1640,34 @@ __global__ __launch_bounds__(kBlock) void k_validate(const long long* row_ptr, i
   if (__ballot(bad_w) && lane_id() == 0) set_status(ctl, OG_ERR_NEGATIVE_WEIGHT);
 }
 
+// OG_FLAG_VALIDATE with a pull direction, after k_validate has passed: the
+// graph must be symmetric (each edge (u, v, w) has a reverse (v, u, w)),
+// since a pull round reads a vertex's row as its in-edges.  The multiset of
+// edges equals the multiset of reversed edges exactly when the sums of a
+// 64-bit hash over both agree (up to hash collisions); the hash is the
+// SplitMix64 finaliser of the packed triple.  One thread per row.
+__device__ __forceinline__ unsigned long long edge_hash(unsigned u, unsigned v, unsigned w) {
+  unsigned long long x = ((unsigned long long)u << 32 | v) ^ ((unsigned long long)w * 0x9E3779B97F4A7C15ull);
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__global__ __launch_bounds__(kBlock) void k_validate_sym(const long long* row_ptr, int n, const int* col, const int* w,
+                                                          Ctl* ctl) {
+  unsigned long long acc = 0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+    for (long long e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      const unsigned v = (unsigned)col[e], wt = w ? (unsigned)w[e] : 0u;
+      acc += edge_hash((unsigned)u, v, wt) - edge_hash(v, (unsigned)u, wt);
+    }
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane_id() == 0 && acc) atomicAdd(&ctl->sym.v, acc);
+}
+__global__ void k_validate_sym_verdict(Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && ctl->sym.v != 0) set_status(ctl, OG_ERR_INVALID_ARG);
+}
+
 // Persistent engine: one cooperative launch; rounds separated by a
 // device-wide barrier whose last arriver takes the bucket decision.  A lazy
 // round has a second barrier between recording the changes and filing them.
@@ -1294,7 +1678,13 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   if (threadIdx.x == 0) load_control<W>(a, s);
   __syncthreads();
   while (!s.done) {
-    run_round<W>(a, s, c);
+    if (W::kPull && s.pull) {
+      run_mark<W>(a, s, c);
+      round_barrier<W>(a, s, c, true, false);
+      run_pull<W>(a, s, c);
+    } else {
+      run_round<W>(a, s, c);
+    }
     if (a.lazy) {
       round_barrier<W>(a, s, c, true, false);
       run_flush<W>(a, s, c);
@@ -1307,8 +1697,10 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
 }
 
 // Host-driven engine: one launch per round (two for a lazy round: phase 0
-// records, phase 1 files); the last workgroup to finish the round takes the
-// bucket decision for the next launch.
+// records, phase 1 files; three with a pull instantiation: phase 0 pushes or
+// marks the frontier, phase 1 pulls or does nothing, phase 2 files); the
+// last workgroup to finish the round takes the bucket decision for the next
+// launch.
 template <class W>
 __global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
   __shared__ Smem s;
@@ -1316,6 +1708,20 @@ __global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
   if (threadIdx.x == 0) load_control<W>(a, s);
   __syncthreads();
   if (s.done) return;
+  if constexpr (W::kPull) {
+    if (phase == 0) {
+      if (s.pull) run_mark<W>(a, s, c);
+      else run_round<W>(a, s, c);
+    } else if (phase == 1) {
+      if (!s.pull) return;
+      run_pull<W>(a, s, c);
+    } else {
+      run_flush<W>(a, s, c);
+    }
+    round_barrier<W>(a, s, c, false, phase == 2);
+    flush_counters(a, c);
+    return;
+  }
   if (phase == 0) {
     run_round<W>(a, s, c);
     round_barrier<W>(a, s, c, false, !a.lazy);
@@ -1482,6 +1888,8 @@ struct DeviceInfo {
   int occ_float = 0;  // co-resident k_persistent<FloatW> workgroups per CU
   int occ_core = 0;   // co-resident k_persistent<CoreW> workgroups per CU
   int occ_split = 0;  // co-resident k_persistent<SplitW> workgroups per CU
+  int occ_pull = 0;   // co-resident k_persistent<PullW> workgroups per CU
+  int occ_core_pull = 0;  // co-resident k_persistent<CorePullW> workgroups per CU
   int coop = 0;
   bool valid = false;
 };
@@ -1503,6 +1911,11 @@ bool device_info(int dev, DeviceInfo* out) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_core, k_persistent<CoreW>, kBlock, 0) != hipSuccess)
       return false;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_split, k_persistent<SplitW>, kBlock, 0) != hipSuccess)
+      return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_pull, k_persistent<PullW>, kBlock, 0) != hipSuccess)
+      return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_core_pull, k_persistent<CorePullW>, kBlock, 0) !=
+        hipSuccess)
       return false;
     di.valid = true;
   }
@@ -1566,6 +1979,10 @@ size_t table_bytes(const Shape& sh) {
 
 bool split_on(const og_schedule* r, const Shape& sh) { return !sh.core && (r->flags & OG_FLAG_LIGHT_HEAVY); }
 
+int pull_mode(const og_schedule* r) {
+  return (r->flags & OG_FLAG_DENSE_PULL) ? kPullAlways : (r->flags & OG_FLAG_HYBRID_DIRECTION) ? kPullHybrid : kPullNever;
+}
+
 // Per-vertex int arrays after the queues: lazy change flags / counts and
 // the change buffer (lazy), peel marks (k-core); each 256-byte aligned.
 size_t vec_bytes(long long n) { return ((size_t)n * sizeof(int) + 255) & ~(size_t)255; }
@@ -1581,6 +1998,9 @@ size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   // light/heavy split: col and w copies, light counts, long-row list, bucket
   // stamps and two heavy lists of (v, 0) entries
   if (split_on(r, sh)) b += 2 * vec_bytes(g->m) + 2 * vec_bytes(g->n) + vec_bytes(nv) + 4 * vec_bytes(nv);
+  // pull direction: frontier bitmap and the long rows' slices
+  if (pull_mode(r) != kPullNever)
+    b += (sh.core ? vec_bytes((nv + 31) / 32) : vec_bytes(2 * nv)) + vec_bytes(2 * (long long)slice_cap(g->m));
   return b;
 }
 
@@ -1594,8 +2014,13 @@ bool schedule_ok(const og_schedule* s) {
   if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS && s->engine != OG_ENGINE_GRAPH_ROUNDS)
     return false;
   if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
-  if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY)) return false;
+  if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL |
+                   OG_FLAG_HYBRID_DIRECTION))
+    return false;
   if ((s->flags & OG_FLAG_LIGHT_HEAVY) && s->update == OG_LAZY_UPDATE) return false;
+  // a direction other than push: lazy updates only, one direction flag
+  if ((s->flags & OG_FLAG_DENSE_PULL) && (s->flags & OG_FLAG_HYBRID_DIRECTION)) return false;
+  if ((s->flags & (OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION)) && s->update != OG_LAZY_UPDATE) return false;
   return true;
 }
 
@@ -1647,7 +2072,8 @@ template <class W>
 hipGraphExec_t round_graph(const Args& a, int nwg, int group, int dev) {
   RoundGraph& rg = t_round_graph;
   const void* f = (const void*)k_round<W>;
-  const int nodes = group * (a.lazy ? 2 : 1);
+  const int phases = W::kPull ? 3 : (a.lazy ? 2 : 1);  // launches per round
+  const int nodes = group * phases;
   if (rg.exec && rg.func == f && rg.nwg == nwg && rg.nodes == nodes && rg.dev == dev &&
       std::memcmp(&rg.args, &a, sizeof(Args)) == 0)
     return rg.exec;
@@ -1660,7 +2086,7 @@ hipGraphExec_t round_graph(const Args& a, int nwg, int group, int dev) {
   hipGraphNode_t prev = nullptr;
   for (int i = 0; i < nodes; ++i) {
     Args ac = a;
-    int phase = a.lazy ? (i & 1) : 0;
+    int phase = i % phases;
     void* kargs[] = {&ac, &phase};
     hipKernelNodeParams p{};
     p.func = const_cast<void*>(f);
@@ -1711,10 +2137,12 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   if (!device_info(dev, &di)) return fail(OG_ERR_HIP);
   const bool persistent = r.engine == OG_ENGINE_PERSISTENT;
   if (persistent && !di.coop) return fail(OG_ERR_HIP);
-  const int occ = std::is_same<W, FloatW>::value   ? di.occ_float
-                  : std::is_same<W, CoreW>::value  ? di.occ_core
-                  : std::is_same<W, SplitW>::value ? di.occ_split
-                                                   : di.occ_int;
+  const int occ = std::is_same<W, FloatW>::value      ? di.occ_float
+                  : std::is_same<W, CoreW>::value     ? di.occ_core
+                  : std::is_same<W, SplitW>::value    ? di.occ_split
+                  : std::is_same<W, PullW>::value     ? di.occ_pull
+                  : std::is_same<W, CorePullW>::value ? di.occ_core_pull
+                                                      : di.occ_int;
   int maxwg = di.cus * (occ > 0 ? occ : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
   if (persistent && nwg > maxwg) nwg = maxwg;
@@ -1723,6 +2151,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
 
   const long long cap = queue_cap(g, &r, sh);
   int *split_col = nullptr, *split_w = nullptr, *split_l = nullptr, *split_big = nullptr;
+  int2* pull_slices = nullptr;
   char* base = (char*)ws;
   int* table = (int*)(base + kCtlBytes);
   Args a;
@@ -1792,6 +2221,19 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       a.ew = split_w;
       a.lsplit = split_l;
     }
+    if constexpr (W::kPull) {
+      a.pull = pull_mode(&r);
+      if constexpr (W::kCore) {
+        a.fbits = (unsigned*)(base + off);
+        off += vec_bytes(((long long)a.n + 31) / 32);
+      } else {
+        a.front = (int2*)(base + off);
+        off += vec_bytes(2 * (long long)a.n);
+      }
+      pull_slices = (int2*)(base + off);
+      a.slices = pull_slices;
+      off += vec_bytes(2 * (long long)slice_cap(g->m));
+    }
   }
 
   const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
@@ -1810,7 +2252,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   }
   const int fill_grid = di.cus * 8;
   const int src_grid = (sh.nsrc + kBlock - 1) / kBlock;
-  if constexpr (std::is_same<W, CoreW>::value) {
+  if constexpr (W::kCore) {
     hipLaunchKernelGGL(k_zero_ctl, dim3(16), dim3(kBlock), 0, stream, a.ctl);
     hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
     hipLaunchKernelGGL(k_init_core, dim3(fill_grid), dim3(kBlock), 0, stream, a);
@@ -1820,18 +2262,37 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     hipLaunchKernelGGL(k_init_sources<W>, dim3(src_grid), dim3(kBlock), 0, stream, a);
   }
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);
+  if constexpr (W::kPull) {
+    if constexpr (W::kCore)
+      hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, (int*)a.fbits, ((long long)a.n + 31) / 32, 0);
+    else
+      hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, (int*)a.front, 2 * (long long)a.n, 0);
+    hipLaunchKernelGGL(k_init_pull, dim3(1), dim3(kWave), 0, stream, a);
+  }
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
   if (r.flags & OG_FLAG_VALIDATE) {
     // checked before anything reads the graph's structure; a bad graph
     // returns here with nothing else launched
     hipLaunchKernelGGL(k_validate, dim3(fill_grid), dim3(kBlock), 0, stream, (const long long*)g->row_ptr, g->n,
-                       g->col, std::is_same<W, CoreW>::value ? nullptr : g->w, (long long)g->m, a.ctl);
+                       g->col, W::kCore ? nullptr : g->w, (long long)g->m, a.ctl);
     unsigned hs[32];  // the status line
     if (hipMemcpyAsync(hs, &a.ctl->status, sizeof(hs), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return fail(OG_ERR_HIP);
     if (hs[0] != 0) return fail((og_status)(int)hs[0]);
+    if constexpr (W::kPull) {
+      // the rows are well formed: check that the graph is symmetric
+      hipLaunchKernelGGL(k_validate_sym, dim3(fill_grid), dim3(kBlock), 0, stream, (const long long*)g->row_ptr,
+                         g->n, g->col, W::kCore ? nullptr : g->w, a.ctl);
+      hipLaunchKernelGGL(k_validate_sym_verdict, dim3(1), dim3(kWave), 0, stream, a.ctl);
+      if (hipMemcpyAsync(hs, &a.ctl->status, sizeof(hs), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess)
+        return fail(OG_ERR_HIP);
+      if (hs[0] != 0) return fail((og_status)(int)hs[0]);
+    }
   }
+  if constexpr (W::kPull)  // reads the rows: after their validation
+    hipLaunchKernelGGL(k_pull_slices, dim3(fill_grid), dim3(kBlock), 0, stream, a, pull_slices);
   if constexpr (W::kSplit) {
     hipLaunchKernelGGL(k_split_small, dim3(fill_grid), dim3(kBlock), 0, stream, a, split_col, split_w, split_l,
                        split_big);
@@ -1850,6 +2311,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     // launch after completion returns at once.  OG_ENGINE_GRAPH_ROUNDS
     // replays one executable hipGraph holding the group's launches.
     const int group = 32;
+    const int phases = W::kPull ? 3 : (a.lazy ? 2 : 1);  // launches per round
     int done = 0;
     long long launched = 0;
     const long long cap_launches = r.max_rounds > 0 ? (long long)r.max_rounds + group : (1LL << 40);
@@ -1862,10 +2324,8 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       if (exec) {
         if (hipGraphLaunch(exec, stream) != hipSuccess) return fail(OG_ERR_HIP);
       } else {
-        for (int i = 0; i < group; ++i) {
-          hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 0);
-          if (a.lazy) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, 1);
-        }
+        for (int i = 0; i < group; ++i)
+          for (int ph = 0; ph < phases; ++ph) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, ph);
       }
       launched += group;
       unsigned hd[64];  // the Control line and the status line
@@ -1877,7 +2337,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     }
   }
   if (timing) (void)hipEventRecord(t_timers.ev[2], stream);
-  if constexpr (std::is_same<W, CoreW>::value) {
+  if constexpr (W::kCore) {
     if (stats) hipLaunchKernelGGL(k_pred_edges<IntW>, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
   } else if (pred) {
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n, kInf);
@@ -1941,6 +2401,11 @@ og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, cons
   if (s->flags & OG_FLAG_LIGHT_HEAVY) {
     if constexpr (std::is_same<W, IntW>::value)
       return run<SplitW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
+    return fail(OG_ERR_INVALID_ARG);  // int32 weights only
+  }
+  if (s->flags & (OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION)) {
+    if constexpr (std::is_same<W, IntW>::value)
+      return run<PullW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
     return fail(OG_ERR_INVALID_ARG);  // int32 weights only
   }
   return run<W>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
@@ -2117,6 +2582,9 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
   if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
   const og::Shape sh{1, g->n, false, true};
   if (!og::shape_ok(g, sh)) return fail(OG_ERR_INVALID_ARG);
+  if (r.flags & (OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION))
+    return og::run<og::CorePullW>(g, sh, {}, {}, nullptr, &r, core, nullptr, nullptr, ws, ws_bytes, stats, stream,
+                                  false);
   return og::run<og::CoreW>(g, sh, {}, {}, nullptr, &r, core, nullptr, nullptr, ws, ws_bytes, stats, stream, false);
 }
 

@@ -87,6 +87,16 @@ def test_workspace_bytes():
     evec = (g.m * 4 + 255) // 256 * 256
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s4)) == (65536 + 256 + 12 * 5000 * 8 + 2 * evec
                                                                          + 3 * vec + 4 * vec)
+    # pull direction (lazy only): + frontier marks (SSSP: 8 bytes per vertex; k-core: one bit) and the
+    # long rows' slice list
+    for fl in (og.OG_FLAG_DENSE_PULL, og.OG_FLAG_HYBRID_DIRECTION):
+        s5 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, update=og.OG_LAZY_UPDATE, flags=fl).to_c()
+        marks = (g.n * 8 + 255) // 256 * 256
+        bits = ((g.n + 31) // 32 * 4 + 255) // 256 * 256
+        slices = ((g.m // 2048 + g.m // 8192 + 1) * 8 + 255) // 256 * 256
+        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s5)) == (65536 + 256 + 12 * 5000 * 8 + 2 * vec
+                                                                             + marks + slices)
+        assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s5)) == base + 3 * vec + bits + slices
     lazy_split = og.Schedule(delta=4, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_LIGHT_HEAVY).to_c()
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(lazy_split)) == 0
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s4)) == base + vec
@@ -98,7 +108,9 @@ def test_workspace_bytes():
 
 @pytest.mark.parametrize("field,value", [
     ("delta", 0), ("update", 3), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
-    ("max_rounds", -1), ("flags", 16), ("fusion_threshold", -2),
+    ("max_rounds", -1), ("flags", 64), ("fusion_threshold", -2),
+    # a pull direction needs lazy updates, and takes one direction flag
+    ("flags", 16), ("flags", 32),
 ])
 def test_invalid_schedule_rejected(field, value):
     lib = _lib.load()
@@ -110,6 +122,31 @@ def test_invalid_schedule_rejected(field, value):
     rc = lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), ctypes.c_void_p(0x4000), None,
                      ctypes.c_void_p(0x10000), ctypes.c_size_t(1 << 40), ctypes.byref(st), None)
     assert rc == og.OG_ERR_INVALID_ARG and st.status == rc
+
+
+def test_pull_direction_rules():
+    lib = _lib.load()
+    g = _fake_graph()
+    st = _lib.OgStats()
+    d = ctypes.c_void_p(0x4000)
+    ws = ctypes.c_void_p(0x10000)
+    big = ctypes.c_size_t(1 << 40)
+    E = og.OG_ERR_INVALID_ARG
+    both = og.Schedule(delta=4, update=og.OG_LAZY_UPDATE,
+                       flags=og.OG_FLAG_DENSE_PULL | og.OG_FLAG_HYBRID_DIRECTION).to_c()
+    assert lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(both), d, None, ws, big, ctypes.byref(st), None) == E
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(both)) == 0
+    for fl in (og.OG_FLAG_DENSE_PULL, og.OG_FLAG_HYBRID_DIRECTION):
+        eager = og.Schedule(delta=4, flags=fl).to_c()
+        assert lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(eager), d, None, ws, big, ctypes.byref(st), None) == E
+        assert lib.og_kcore(ctypes.byref(g), ctypes.byref(eager), d, ws, big, ctypes.byref(st), None) == E
+        split = og.Schedule(delta=4, update=og.OG_LAZY_UPDATE, flags=fl | og.OG_FLAG_LIGHT_HEAVY).to_c()
+        assert lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(split), d, None, ws, big, ctypes.byref(st), None) == E
+        # float32 weights have no pull instantiation
+        lazy = og.Schedule(delta=4, update=og.OG_LAZY_UPDATE, flags=fl).to_c()
+        gf = _lib.OgGraphF32(10, 20, 0x1000, 0x2000, 0x3000)
+        assert lib.og_sssp_f32(ctypes.byref(gf), 0, ctypes.byref(lazy), d, None, None, ws, big,
+                               ctypes.byref(st), None) == E
 
 
 def test_invalid_calls_rejected():

@@ -2,7 +2,8 @@
 GPU: the runner is a plain function of the schedule)."""
 import math
 
-from paper_1911_07260_amd import OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, Schedule
+from paper_1911_07260_amd import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_VALIDATE,
+                                   OG_LAZY_UPDATE, Schedule)
 from paper_1911_07260_amd.autotune import Autotuner
 
 
@@ -35,3 +36,22 @@ def test_failing_candidates_are_skipped():
     res = Autotuner(runner).tune(weight_scale=15.0)
     assert res.best.update == OG_EAGER_WITH_FUSION
     assert any(not t.ok for t in res.trials)
+
+
+def test_lazy_and_direction_candidates():
+    """With lazy=True the search also times the lazy update, pushing and with
+    the hybrid direction, and returns the direction flag it chose next to the
+    caller's own flags."""
+    def runner(s):
+        c = cost(Schedule(**{**s.__dict__, "update": OG_EAGER_WITH_FUSION}))
+        if s.update == OG_LAZY_UPDATE:
+            c -= 4.0 if s.flags & OG_FLAG_HYBRID_DIRECTION else 1.0
+        return c
+    res = Autotuner(runner, base=Schedule(flags=OG_FLAG_VALIDATE)).tune(weight_scale=15.0, lazy=True)
+    assert res.best.update == OG_LAZY_UPDATE
+    assert res.best.flags == OG_FLAG_VALIDATE | OG_FLAG_HYBRID_DIRECTION
+    assert any(t.schedule["update"] == OG_LAZY_UPDATE and not t.schedule["flags"] & OG_FLAG_HYBRID_DIRECTION
+               for t in res.trials)
+    # without lazy=True the eager strategies only
+    res = Autotuner(runner).tune(weight_scale=15.0)
+    assert res.best.update == OG_EAGER_WITH_FUSION and res.best.flags == 0
