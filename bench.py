@@ -644,10 +644,15 @@ def main() -> int:
             "traffic": traffic,
             "alg_bytes_per_launch": round(alg_bytes),
             "kernel_ms": round(engine_ms, 3),
+            # the counted bytes over the same kernel time, against the same peak
+            "traffic_frac": (round(traffic / (engine_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+                             if traffic is not None else None),
         },
         "phases_ms": {"init": round(init_ms, 3), "engine": round(engine_ms, 3), "pred": round(pred_ms, 3)},
         "rounds": int(np.mean([s["rounds"] for s in stats])),
         "relaxations_per_query": int(np.mean([s["relaxations"] for s in stats])),
+        "improvements_per_query": int(np.mean([s["improvements"] for s in stats])),
+        "pushes_per_query": int(np.mean([s["pushes_local"] + s["pushes_global"] for s in stats])),
         "variants": variants,
         "cpu_baseline": cpu,
         "parity_on_cpu_sample": parity,

@@ -16,7 +16,10 @@
  *     and A* (priority = distance so far + per-vertex estimate).
  * The schedule fields mirror the scheduling-language table of section 4.2
  * (configApplyPriorityUpdate, ...Delta, configBucketFusionThreshold,
- * configNumBuckets).
+ * configNumBuckets); the traversal direction (configApplyDirection) is a
+ * schedule flag.  Also: the lazy bucket update (section 3.1) and k-core
+ * decomposition (section 6.1), batched queries, and a float32 variant with
+ * a backward pass.
  *
  * Conventions
  *   - Every array argument is DEVICE memory owned by the caller, except
