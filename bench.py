@@ -4,15 +4,17 @@ Workload: 4096 x 4096 road-like grid (16,777,216 vertices, ~50.4 M directed
 edges; each grid edge kept with p = 0.75, 0.1 % long-range edges within 64
 grid steps, weights llround(10 * length * U(1, 2))), seed 0; 8 sources drawn
 with seed 1.  One step = one full single-source query through the C ABI:
-initialisation, the bucket engine (all rounds) and the canonical predecessor
-pass, with the graph already resident in HBM.
+initialisation, the bucket engine (all rounds; fused, Delta 512, degree-
+binned load balancing) and the canonical predecessor pass, with the graph
+already resident in HBM.
 
 Prints one JSON line.  `value` is whole-job GTEPS = (sum over timed steps of
 the out-degrees of reached vertices) / wall time of the timed steps.
 
-Extra legs (outside the timed region): unfused and host-driven variants on
-the same sources, the CPU oracle on a bounded sample (cpu_baseline), and
-bit-exact parity of the GPU distances on those sampled sources.
+Extra legs (outside the timed region): unfused, host-driven, lazy and
+flat-expansion variants on the same sources, a batched launch, the CPU
+oracle on a bounded sample (cpu_baseline), and bit-exact parity of the GPU
+distances on those sampled sources.
 
     python bench.py [--steps K] [--warmup W] [--delta D] [--no-cpu]
     python bench.py --copy-calibration   # plain 1 GiB device copy, for PMC scaling
@@ -120,6 +122,8 @@ def workload_rmat(args) -> int:
             ("sssp_fused", None, og.sssp, og.Schedule(delta=args.rmat_delta, flags=og.OG_FLAG_TIMING)),
             ("sssp_lazy", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
                                                      flags=og.OG_FLAG_TIMING)),
+            ("sssp_degree_bins", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_EAGER_NO_FUSION,
+                                                            flags=og.OG_FLAG_TIMING | og.OG_FLAG_DEGREE_BINS)),
             ("sssp_lazy_pull", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
                                                           flags=og.OG_FLAG_TIMING | og.OG_FLAG_DENSE_PULL)),
             ("sssp_lazy_hybrid", None, og.sssp, og.Schedule(delta=args.rmat_delta, update=og.OG_LAZY_UPDATE,
@@ -133,6 +137,8 @@ def workload_rmat(args) -> int:
             ("wbfs", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING)),
             ("wbfs_split", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING
                                                                  | og.OG_FLAG_LIGHT_HEAVY)),
+            ("wbfs_degree_bins", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, flags=og.OG_FLAG_TIMING
+                                                                       | og.OG_FLAG_DEGREE_BINS)),
             ("wbfs_lazy", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, update=og.OG_LAZY_UPDATE,
                                                                 flags=og.OG_FLAG_TIMING)),
             ("wbfs_lazy_pull", (g.w % 23) + 1, og.wbfs, og.Schedule(delta=1, update=og.OG_LAZY_UPDATE,
@@ -481,17 +487,22 @@ def main() -> int:
         _, _, st = og.sssp(dg, srcs[i % len(srcs)], sched, ws=ws, out_dist=dist, out_pred=pred)
         return st
 
+    # the single-query road schedules balance load with degree bins (lane <=
+    # 4 edges, wavefront <= 64, workgroup above); "fused_flat" is the
+    # headline without them
+    TB = og.OG_FLAG_TIMING | og.OG_FLAG_DEGREE_BINS
+
     sweep = None
     if args.delta <= 0:
         # the configuration sweeps Delta; the headline runs at the fastest one
         sweep = {}
         for dlt in (256, 512, 1024, 2048, 4096):
-            sch = og.Schedule(delta=dlt, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING)
+            sch = og.Schedule(delta=dlt, update=og.OG_EAGER_WITH_FUSION, flags=TB)
             step(0, sch)
             sweep[dlt] = round(float(np.mean([step(i, sch)["engine_ms"] for i in range(2)])), 3)
         args.delta = min(sweep, key=sweep.get)
         print(f"[bench] delta sweep (engine ms): {sweep} -> {args.delta}", file=sys.stderr, flush=True)
-    fused = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING)
+    fused = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=TB)
 
     for i in range(args.warmup):
         step(i, fused)
@@ -525,25 +536,29 @@ def main() -> int:
     if not args.no_variants:
         nvar = min(2, len(srcs))
         for name, sched in (
-            ("unfused_persistent", og.Schedule(delta=args.delta, update=og.OG_EAGER_NO_FUSION,
-                                               flags=og.OG_FLAG_TIMING)),
+            ("unfused_persistent", og.Schedule(delta=args.delta, update=og.OG_EAGER_NO_FUSION, flags=TB)),
             ("fused_host_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION,
-                                              engine=og.OG_ENGINE_HOST_ROUNDS, flags=og.OG_FLAG_TIMING)),
+                                              engine=og.OG_ENGINE_HOST_ROUNDS, flags=TB)),
             ("unfused_host_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_NO_FUSION,
-                                                engine=og.OG_ENGINE_HOST_ROUNDS, flags=og.OG_FLAG_TIMING)),
+                                                engine=og.OG_ENGINE_HOST_ROUNDS, flags=TB)),
             ("fused_graph_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION,
-                                               engine=og.OG_ENGINE_GRAPH_ROUNDS, flags=og.OG_FLAG_TIMING)),
+                                               engine=og.OG_ENGINE_GRAPH_ROUNDS, flags=TB)),
             ("unfused_graph_rounds", og.Schedule(delta=args.delta, update=og.OG_EAGER_NO_FUSION,
-                                                 engine=og.OG_ENGINE_GRAPH_ROUNDS, flags=og.OG_FLAG_TIMING)),
-            ("lazy_persistent", og.Schedule(delta=args.delta, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_TIMING)),
+                                                 engine=og.OG_ENGINE_GRAPH_ROUNDS, flags=TB)),
+            ("lazy_persistent", og.Schedule(delta=args.delta, update=og.OG_LAZY_UPDATE, flags=TB)),
+            # flat expansion instead of degree bins, on all the headline's
+            # sources (comparable with "fused")
+            ("fused_flat", og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING)),
         ):
             sts = []
+            nv = len(srcs) if name == "fused_flat" else nvar
+            step(0, sched)  # warm-up: the first launch of an instantiation loads its code
             torch.cuda.synchronize()
             t = time.perf_counter()
-            for i in range(nvar):
+            for i in range(nv):
                 sts.append(step(i, sched))
             torch.cuda.synchronize()
-            ms = (time.perf_counter() - t) / nvar * 1e3
+            ms = (time.perf_counter() - t) / nv * 1e3
             variants[name] = {"ms_per_query": round(ms, 3),
                               "engine_ms": round(float(np.mean([s["engine_ms"] for s in sts])), 3),
                               "rounds": int(np.mean([s["rounds"] for s in sts]))}
@@ -557,6 +572,8 @@ def main() -> int:
         # in one persistent launch, distances and predecessors for all
         nq = args.batch
         bsrcs = [int(s) for s in gg.pick_sources(g, nq, seed=1)]
+        # flat expansion: a batch launch is made of full global batches, where
+        # it beats the degree bins (measured 4.76 vs 5.31 ms per query)
         bsched = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=og.OG_FLAG_TIMING,
                              queue_capacity=max(1 << 22, nq * (1 << 21)))
         bws = og.Workspace(dev)
@@ -632,11 +649,12 @@ def main() -> int:
                         f"<=64 steps, w=llround(10*len*U(1,2)), seed 0), {len(srcs)} sources (seed 1)",
             "n": g.n, "m": g.m, "delta": args.delta, "delta_sweep_engine_ms": sweep,
             "update": "eager_with_fusion", "engine": "persistent",
+            "load_balance": "degree bins (lane <= 4 edges, wavefront <= 64, workgroup above)",
             "outputs": "dist + canonical pred",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_persistent",
+            "kernel": "k_persistent<BinW>",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -113,6 +113,18 @@ typedef int32_t og_status;
                                mean degree, exceed m/20) and pushes otherwise.
                                Same requirements; not together with
                                OG_FLAG_DENSE_PULL.                            */
+#define OG_FLAG_DEGREE_BINS 64u /* degree-binned load balancing: within each
+                               batch of queue entries, a vertex of at most
+                               schedule.bin_thread edges gets a fixed group of
+                               4 lanes, one edge each (no scan, no search),
+                               one of at most schedule.bin_wave edges one
+                               wavefront, 64 edges at a time, and larger ones
+                               the whole workgroup (a block scan spreads their
+                               edges over all lanes, the default for every
+                               vertex without this flag).  int32 weights
+                               (og_sssp_f32 returns OG_ERR_INVALID_ARG); not
+                               together with OG_FLAG_LIGHT_HEAVY or a pull
+                               direction; og_kcore ignores it.               */
 
 /* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
 #define OG_EAGER_NO_FUSION 0
@@ -162,6 +174,11 @@ typedef struct og_schedule {
   uint32_t flags;           /* OG_FLAG_*                                      */
   int64_t queue_capacity;   /* entries per global queue (0 = n + m/8; og_kcore:
                                2n + m/8)                                      */
+  int32_t bin_thread;       /* OG_FLAG_DEGREE_BINS: largest degree relaxed by
+                               one lane (0 = 4; at most 4)                    */
+  int32_t bin_wave;         /* OG_FLAG_DEGREE_BINS: largest degree relaxed by
+                               one wavefront (0 = 64; below bin_thread: no
+                               wavefront bin)                                 */
 } og_schedule;
 
 /* Per-call counters (host struct). */
@@ -197,7 +214,8 @@ int32_t og_version(void);
 const char* og_status_string(og_status s);
 
 /* Overwrites every field of *s with the defaults (delta 1, fusion on,
- * threshold 1024, 16 window buckets, persistent engine, no limits). */
+ * threshold 1024, 16 window buckets, persistent engine, no limits, degree
+ * bins 4 / 64). */
 og_status og_default_schedule(og_schedule* s);
 
 /* Workspace bytes og_sssp & co. need for this graph and schedule (0 if the

@@ -17,7 +17,7 @@ The Schedule selects the update mode (eager with or without bucket fusion,
 lazy), the engine (persistent kernel, one launch per round, or rounds
 replayed from a captured hipGraph) and flags (structure validation, light /
 heavy edge split, dense-pull or hybrid traversal direction with lazy
-updates).  ``diff`` holds the FP32 forward and backward passes
+updates, degree-binned load balancing).  ``diff`` holds the FP32 forward and backward passes
 (og_sssp_f32, og_sssp_backward_f32) and an autograd Function over them;
 ``autotune`` searches Delta and the fusion threshold on the device.
 
@@ -34,8 +34,8 @@ import torch
 from . import _lib
 from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_GRAPH_ROUNDS, OG_ENGINE_HOST_ROUNDS,
                    OG_ENGINE_PERSISTENT, OG_ERR_HIP, OG_ERR_INTERNAL, OG_ERR_INVALID_ARG, OG_ERR_NEGATIVE_WEIGHT,
-                   OG_ERR_OVERFLOW, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE, OG_FLAG_ASYNC, OG_FLAG_DENSE_PULL,
-                   OG_FLAG_HYBRID_DIRECTION, OG_FLAG_LIGHT_HEAVY, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, OG_OK,
+                   OG_ERR_OVERFLOW, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE, OG_FLAG_ASYNC, OG_FLAG_DEGREE_BINS,
+                   OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_LIGHT_HEAVY, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, OG_OK,
                    OgError, OgGraph, OgSchedule, OgStats)
 
 INF = 2**31 - 1
@@ -58,6 +58,8 @@ class Schedule:
     workgroups: int = 0
     flags: int = 0
     queue_capacity: int = 0
+    bin_thread: int = 0
+    bin_wave: int = 0
 
     @property
     def fused(self) -> bool:

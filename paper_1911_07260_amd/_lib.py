@@ -27,6 +27,7 @@ OG_FLAG_TIMING = 4
 OG_FLAG_LIGHT_HEAVY = 8
 OG_FLAG_DENSE_PULL = 16
 OG_FLAG_HYBRID_DIRECTION = 32
+OG_FLAG_DEGREE_BINS = 64
 
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1
@@ -68,6 +69,8 @@ class OgSchedule(ctypes.Structure):
         ("workgroups", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("queue_capacity", ctypes.c_int64),
+        ("bin_thread", ctypes.c_int32),
+        ("bin_wave", ctypes.c_int32),
     ]
 
 

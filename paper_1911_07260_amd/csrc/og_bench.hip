@@ -11,6 +11,7 @@
 //            [--steps 8] [--warmup 2] [--update fused|unfused|lazy]
 //            [--engine persistent|host|graph] [--window K] [--kcore]
 //            [--direction push|pull|hybrid]   (pull and hybrid need --update lazy)
+//            [--bins]   (degree-binned load balancing)
 //            [--copy-calibration]
 //
 // --copy-calibration instead runs a plain copy kernel over 1 GiB three
@@ -77,6 +78,7 @@ int main(int argc, char** argv) {
   int update = OG_EAGER_WITH_FUSION, engine = OG_ENGINE_PERSISTENT;
   bool rmat = false, kcore = false;
   uint32_t direction = 0;
+  bool bins = false;
   for (int i = 1; i < argc; ++i) {
     auto next = [&](void) -> const char* {
       if (i + 1 >= argc) { std::fprintf(stderr, "missing value for %s\n", argv[i]); std::exit(2); }
@@ -105,6 +107,7 @@ int main(int argc, char** argv) {
       const char* d = next();
       direction = !std::strcmp(d, "pull") ? OG_FLAG_DENSE_PULL : !std::strcmp(d, "hybrid") ? OG_FLAG_HYBRID_DIRECTION : 0u;
     }
+    else if (!std::strcmp(argv[i], "--bins")) bins = true;
     else if (!std::strcmp(argv[i], "--copy-calibration")) return copy_calibration();
     else { std::fprintf(stderr, "unknown argument %s\n", argv[i]); return 2; }
   }
@@ -144,7 +147,7 @@ int main(int argc, char** argv) {
   s.delta = delta;
   s.update = update;
   s.engine = engine;
-  s.flags = OG_FLAG_TIMING | direction;
+  s.flags = OG_FLAG_TIMING | direction | (bins ? OG_FLAG_DEGREE_BINS : 0u);
   if (window > 0) s.window_buckets = window;
   const size_t wsb = kcore ? og_workspace_bytes_kcore(&g, &s) : og_workspace_bytes(&g, &s);
   void* ws = nullptr;

@@ -105,6 +105,10 @@ __host__ __device__ inline unsigned long long slice_cap(long long m) {
 // this bit set when the vertex also has heavy edges.
 constexpr int kHeavyBit = 1 << 30;
 constexpr int kDegMask = kHeavyBit - 1;
+// Degree bins: the lane bin holds vertices of up to kBinLane edges, each
+// edge on a fixed slot of its own.
+constexpr int kBinLane = 4;
+constexpr int kDefaultBinWave = 64;
 enum : int {
   kStRelax, kStImprove, kStPushLocal, kStPushGlobal, kStFar, kStBatches, kStReachedV, kStReachedE, kStChain, kStCount
 };
@@ -197,6 +201,8 @@ struct Args {
   int2* heavy;        // 2 lists of hcap (v, 0) entries: vertices settled in a bucket
   unsigned hcap;
   long long m;
+  int bin_thread;    // degree bins (BinW): lane bin up to this degree (<= kBinLane)
+  int bin_wave;      // degree bins (BinW): wavefront bin up to this degree
   int pull;          // direction: kPullNever, kPullAlways or kPullHybrid
   int2* front;       // [n] pull, SSSP: (round stamp, distance) of the round's frontier vertices
   unsigned* fbits;   // [ceil(n / 32)] pull, k-core: bitmap of the vertices peeled in the round
@@ -279,6 +285,7 @@ struct IntW {
   static constexpr bool kSplit = false;
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
+  static constexpr bool kBin = false;
   // nd = d + w; false (and a status) for a negative weight or a sum that
   // reaches INT32_MAX
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
@@ -309,6 +316,7 @@ struct FloatW {
   static constexpr bool kSplit = false;
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
+  static constexpr bool kBin = false;
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
     const float w = __int_as_float(wraw);
     if (!(w >= 0.0f) || w == __int_as_float(kInfBits)) {  // negative, NaN or infinite
@@ -363,6 +371,15 @@ struct PullW : IntW {
 };
 struct CorePullW : CoreW {
   static constexpr bool kPull = true;
+};
+
+// Degree-binned load balancing: within a batch, a vertex of at most
+// bin_thread edges (<= kBinLane) is relaxed by kBinLane lanes of fixed
+// slots, one of at most bin_wave edges by its wavefront, and larger ones by
+// the whole workgroup (the flat expansion of the other instantiations).
+// int32 distances.
+struct BinW : IntW {
+  static constexpr bool kBin = true;
 };
 
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
@@ -671,6 +688,201 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
   }
 }
 
+// One edge of the binned routine (the same steps as the edge loop of
+// process_batch): u = ub + voff, entry distance dsrc, the vertex's current
+// distance dnow (the per-edge staleness check of ring entries).  Returns
+// whether the atomic minimum improved u; *nd, *b, *r0, *rdeg as for
+// route_push.
+template <class W>
+__device__ __forceinline__ bool relax_edge(const Args& a, const Smem& s, Counters& c, int ub, int wt, int dsrc,
+                                           int dnow, int u, bool prefilter, unsigned* nd, unsigned* b, int* r0,
+                                           int* rdeg) {
+  c.relax++;
+  int ndi = 0;
+  if (!(dsrc <= dnow && W::add(a, dsrc, wt, &ndi))) return false;
+  *nd = (unsigned)ndi;
+  const unsigned key = W::key(a, u, ndi);
+  bool go = !(a.tgts && key >= (unsigned)s.tb[query_of(a, u)]);  // cannot improve the target
+  if (go && prefilter) go = ndi < a.dist[u];
+  if (!go) return false;
+  unsigned bk = W::bucket(a, key);
+  if (bk < s.cur) bk = s.cur;  // only an inconsistent A* estimate gets here
+  *b = bk;
+  long long q0 = 0, q1 = 0;
+  if (a.fused && bk == s.cur) {  // the next hop's row, fetched alongside the atomic
+    q0 = a.row_ptr[ub];
+    q1 = a.row_ptr[ub + 1];
+  }
+  const int old = atomicMin(&a.dist[u], ndi);
+  if (ndi >= old) return false;
+  c.improve++;
+  *r0 = (int)q0;
+  *rdeg = (int)(q1 - q0);
+  return true;
+}
+
+// Files the lanes' improved vertices (all 64 lanes call it together): lazy
+// update records them, eager update routes them.
+__device__ __forceinline__ void finish_edges(const Args& a, Smem& s, Counters& c, bool has, int u, unsigned nd,
+                                             unsigned b, int r0, int rdeg) {
+  if (a.lazy) {
+    const bool first = has && atomicExch(&a.aux[u], 1) == 0;
+    wave_append_buf(a, first, u);
+  } else {
+    route_push(a, s, c, has, u, (int)nd, b, r0, rdeg);
+  }
+}
+
+// process_batch with degree bins (BinW).  The entry checks are those of
+// process_batch.  Then:
+//   - lane bin (degree <= bin_thread): kBinLane lanes per vertex, one edge
+//     each, found by a division instead of a scan and a search;
+//   - wavefront bin (degree <= bin_wave): each wavefront takes the bin's
+//     vertices of its own 64 lanes (no workgroup barrier) and relaxes each
+//     row 64 edges at a time;
+//   - workgroup bin: the remaining rows are expanded over the workgroup by
+//     a block scan and a binary search, as in process_batch.
+template <class W>
+__device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds) {
+  const int tid = threadIdx.x;
+  const int v = ent.x;
+  const int d = ent.y;
+  int deg = 0, start = 0, voff = 0;
+  bool repush = false;
+  unsigned rb = 0;
+  if (v >= 0) {
+    const int vb = a.reps == 1 ? v : (int)((unsigned)v % (unsigned)a.nbase);
+    voff = v - vb;
+    if (from_lds) {
+      start = ent.z;
+      deg = ent.w;
+    } else {
+      const int cv = a.dist[v];
+      const long long r0 = a.row_ptr[vb];
+      const long long r1 = a.row_ptr[vb + 1];
+      const unsigned key = W::key(a, v, d);
+      bool live = d <= cv;
+      if (live) {
+        rb = W::bucket(a, key);
+        if (rb > s.cur) {
+          repush = true;  // a far-list entry that belongs to a later bucket
+          live = false;
+        }
+      }
+      if (live && a.tgts && key >= (unsigned)s.tb[query_of(a, v)]) live = false;  // cannot improve the target
+      if (live) {
+        start = (int)r0;
+        deg = (int)(r1 - r0);
+      }
+    }
+  }
+  {
+    int tgt = 0;
+    if (repush) tgt = rb < s.win_hi ? (int)(rb & (unsigned)(a.K - 1)) : a.K + 1;
+    wave_push_global(a, s, c, repush, tgt, v, d, rb);
+  }
+  const int lane_max = a.bin_thread < kBinLane ? a.bin_thread : kBinLane;
+  const bool in_lane = deg > 0 && deg <= lane_max;
+  const bool in_wave = deg > lane_max && deg <= a.bin_wave;
+  const bool prefilter = !from_lds;
+  // Ring entries get their staleness check per edge: the vertex's current
+  // distance is loaded together with the edge (global entries were checked
+  // above).
+
+  // lane bin: kBinLane lanes per vertex, slot e = kBinLane * (entry index)
+  // + k holds edge k of that entry (no scan, no search), so every edge of
+  // the bin is in flight at once.  The batch arrays hold every entry's row
+  // start, distance, vertex and offset for all three bins; boff holds the
+  // lane bin's degrees (a wavefront-bin entry: minus its degree).
+  s.bstart[tid] = start;
+  s.boff[tid] = in_lane ? deg : (in_wave ? -deg : 0);
+  s.bd[tid] = d;
+  s.bv[tid] = v;
+  s.bvo[tid] = voff;
+  __syncthreads();
+  {
+    const int slots = s.nb * kBinLane;
+    for (int base = 0; base < slots; base += kBlock) {
+      const int e = base + tid;
+      const int j = e / kBinLane, k = e % kBinLane;
+      bool has = false;
+      int u = 0, r0 = 0, rdeg = 0;
+      unsigned nd = 0, b = 0;
+      if (e < slots && k < s.boff[j]) {
+        const int edge = s.bstart[j] + k;
+        const int ubk = a.col[edge];
+        const int wk = a.w[edge];
+        const int dn = from_lds ? a.dist[s.bv[j]] : s.bd[j];
+        u = ubk + s.bvo[j];
+        has = relax_edge<W>(a, s, c, ubk, wk, s.bd[j], dn, u, prefilter, &nd, &b, &r0, &rdeg);
+      }
+      finish_edges(a, s, c, has, u, nd, b, r0, rdeg);
+    }
+  }
+
+  // wavefront bin: the wavefront takes the bin's vertices of its own 64
+  // lanes one at a time, each vertex's fields read once into scalar
+  // registers (no further workgroup barrier)
+  {
+    const int wbase = (tid / kWave) * kWave;
+    unsigned long long wm = __ballot(in_wave);
+    while (wm) {
+      const int j = wbase + __ffsll((long long)wm) - 1;
+      wm &= wm - 1;
+      const int e0 = __builtin_amdgcn_readfirstlane(s.bstart[j]);
+      const int dg = -__builtin_amdgcn_readfirstlane(s.boff[j]);
+      const int dj = __builtin_amdgcn_readfirstlane(s.bd[j]);
+      const int vj = __builtin_amdgcn_readfirstlane(s.bv[j]);
+      const int vo = __builtin_amdgcn_readfirstlane(s.bvo[j]);
+      for (int it = 0; it < dg; it += kWave) {
+        const int k = it + (int)lane_id();
+        unsigned nd = 0, b = 0;
+        int r0 = 0, rdeg = 0, u = 0;
+        bool has = false;
+        if (k < dg) {
+          const int ubk = a.col[e0 + k];
+          const int wk = a.w[e0 + k];
+          const int dn = from_lds ? a.dist[vj] : dj;
+          u = ubk + vo;
+          has = relax_edge<W>(a, s, c, ubk, wk, dj, dn, u, prefilter, &nd, &b, &r0, &rdeg);
+        }
+        finish_edges(a, s, c, has, u, nd, b, r0, rdeg);
+      }
+    }
+  }
+
+  // workgroup bin: flat expansion of the remaining rows
+  const int dflat = in_lane || in_wave ? 0 : deg;
+  int total;
+  const int off = block_excl_scan(dflat, s, &total);  // its barrier also ends the lane bin's use of the arrays
+  if (total == 0) return;
+  s.boff[tid] = off;  // row start, distance, vertex and offset are in place from the lane bin
+  __syncthreads();
+  const int nb = s.nb;
+  for (int base = 0; base < total; base += kBlock) {
+    const int e = base + tid;
+    bool has = false;
+    int u = 0, r0 = 0, rdeg = 0;
+    unsigned nd = 0, b = 0;
+    if (e < total) {
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.boff[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      const int edge = s.bstart[lo] + (e - s.boff[lo]);
+      const int dsrc = s.bd[lo];
+      const int ubk = a.col[edge];
+      const int wk = a.w[edge];
+      const int dn = from_lds ? a.dist[s.bv[lo]] : dsrc;
+      u = ubk + s.bvo[lo];
+      has = relax_edge<W>(a, s, c, ubk, wk, dsrc, dn, u, !from_lds || total > kBlock, &nd, &b, &r0, &rdeg);
+    }
+    finish_edges(a, s, c, has, u, nd, b, r0, rdeg);
+  }
+}
+
 // k-core filing of vertex u at priority p (> the current level, or equal to
 // it for the current bucket).  A priority at or beyond the window goes to
 // the far list only if u is not already filed in that list (the far list is
@@ -919,6 +1131,7 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
       }
     }
     if constexpr (W::kCore) process_batch_core(a, s, c, ent, mode == 1);
+    else if constexpr (W::kBin) process_batch_binned<W>(a, s, c, ent, mode == 1);
     else process_batch<W>(a, s, c, ent, mode == 1);
     c.batches++;
     c.round_batches++;
@@ -1890,6 +2103,7 @@ struct DeviceInfo {
   int occ_split = 0;  // co-resident k_persistent<SplitW> workgroups per CU
   int occ_pull = 0;   // co-resident k_persistent<PullW> workgroups per CU
   int occ_core_pull = 0;  // co-resident k_persistent<CorePullW> workgroups per CU
+  int occ_bin = 0;    // co-resident k_persistent<BinW> workgroups per CU
   int coop = 0;
   bool valid = false;
 };
@@ -1916,6 +2130,8 @@ bool device_info(int dev, DeviceInfo* out) {
       return false;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_core_pull, k_persistent<CorePullW>, kBlock, 0) !=
         hipSuccess)
+      return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_bin, k_persistent<BinW>, kBlock, 0) != hipSuccess)
       return false;
     di.valid = true;
   }
@@ -1949,6 +2165,9 @@ og_schedule resolved(const og_schedule* s) {
   if (r.fusion_threshold <= 0) r.fusion_threshold = kDefaultThreshold;
   if (r.fusion_threshold > kLq) r.fusion_threshold = kLq;
   if (r.window_buckets <= 0) r.window_buckets = kDefaultK;
+  if (r.bin_thread == 0) r.bin_thread = kBinLane;
+  if (r.bin_thread > kBinLane) r.bin_thread = kBinLane;
+  if (r.bin_wave == 0) r.bin_wave = kDefaultBinWave;
   r.window_buckets = pow2_at_least(r.window_buckets < 2 ? 2 : r.window_buckets);
   return r;
 }
@@ -2015,7 +2234,12 @@ bool schedule_ok(const og_schedule* s) {
     return false;
   if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
   if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL |
-                   OG_FLAG_HYBRID_DIRECTION))
+                   OG_FLAG_HYBRID_DIRECTION | OG_FLAG_DEGREE_BINS))
+    return false;
+  if (s->bin_thread < 0 || s->bin_wave < 0) return false;
+  // degree bins are their own instantiation: not with the split or a pull direction
+  if ((s->flags & OG_FLAG_DEGREE_BINS) &&
+      (s->flags & (OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION)))
     return false;
   if ((s->flags & OG_FLAG_LIGHT_HEAVY) && s->update == OG_LAZY_UPDATE) return false;
   // a direction other than push: lazy updates only, one direction flag
@@ -2142,6 +2366,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
                   : std::is_same<W, SplitW>::value    ? di.occ_split
                   : std::is_same<W, PullW>::value     ? di.occ_pull
                   : std::is_same<W, CorePullW>::value ? di.occ_core_pull
+                  : std::is_same<W, BinW>::value      ? di.occ_bin
                                                       : di.occ_int;
   int maxwg = di.cus * (occ > 0 ? occ : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
@@ -2178,6 +2403,8 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   a.cap = (unsigned)cap;
   a.fused = r.update == OG_EAGER_WITH_FUSION;
   a.threshold = (unsigned)r.fusion_threshold;
+  a.bin_thread = r.bin_thread;
+  a.bin_wave = r.bin_wave;
   a.max_rounds = (unsigned)r.max_rounds;
   a.nwg = nwg;
   a.ctl = (Ctl*)base;
@@ -2408,6 +2635,11 @@ og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, cons
       return run<PullW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
     return fail(OG_ERR_INVALID_ARG);  // int32 weights only
   }
+  if (s->flags & OG_FLAG_DEGREE_BINS) {
+    if constexpr (std::is_same<W, IntW>::value)
+      return run<BinW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
+    return fail(OG_ERR_INVALID_ARG);  // int32 weights only
+  }
   return run<W>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
 }
 
@@ -2439,6 +2671,8 @@ og_status og_default_schedule(og_schedule* s) {
   s->fusion_threshold = og::kDefaultThreshold;
   s->window_buckets = og::kDefaultK;
   s->engine = OG_ENGINE_PERSISTENT;
+  s->bin_thread = og::kBinLane;
+  s->bin_wave = og::kDefaultBinWave;
   return OG_OK;
 }
 
@@ -2562,7 +2796,7 @@ size_t og_workspace_bytes_kcore(const og_graph* g, const og_schedule* s) {
   if (!s) return 0;
   og_schedule r = og::resolved(s);
   r.delta = 1;
-  r.flags &= ~OG_FLAG_LIGHT_HEAVY;
+  r.flags &= ~(OG_FLAG_LIGHT_HEAVY | OG_FLAG_DEGREE_BINS);
   if (!og::graph_ok(g, false) || !og::schedule_ok(&r)) return 0;
   return og::ws_bytes_for(g, &r, og::Shape{1, g->n, false, true});
 }
@@ -2577,7 +2811,7 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
   if (!s) return fail(OG_ERR_INVALID_ARG);
   og_schedule r = *s;
   r.delta = 1;  // one bucket per degree value: peeling needs the strict order
-  r.flags &= ~OG_FLAG_LIGHT_HEAVY;
+  r.flags &= ~(OG_FLAG_LIGHT_HEAVY | OG_FLAG_DEGREE_BINS);
   if (!og::graph_ok(g, false) || !og::schedule_ok(&r) || !core || !ws) return fail(OG_ERR_INVALID_ARG);
   if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
   const og::Shape sh{1, g->n, false, true};

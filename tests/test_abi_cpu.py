@@ -56,6 +56,7 @@ def test_default_schedule():
     s = _lib.OgSchedule()
     assert lib.og_default_schedule(ctypes.byref(s)) == 0
     assert s.delta == 1 and s.update == 1 and s.window_buckets == 16 and s.fusion_threshold == 1024
+    assert s.bin_thread == 4 and s.bin_wave == 64
     assert lib.og_default_schedule(None) == og.OG_ERR_INVALID_ARG
 
 
@@ -108,9 +109,11 @@ def test_workspace_bytes():
 
 @pytest.mark.parametrize("field,value", [
     ("delta", 0), ("update", 3), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
-    ("max_rounds", -1), ("flags", 64), ("fusion_threshold", -2),
+    ("max_rounds", -1), ("flags", 128), ("fusion_threshold", -2),
     # a pull direction needs lazy updates, and takes one direction flag
     ("flags", 16), ("flags", 32),
+    # degree bins: non-negative cut-offs, not with the split or a pull direction
+    ("bin_thread", -1), ("bin_wave", -1), ("flags", 64 | 8), ("flags", 64 | 16),
 ])
 def test_invalid_schedule_rejected(field, value):
     lib = _lib.load()
