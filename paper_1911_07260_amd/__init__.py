@@ -19,7 +19,8 @@ replayed from a captured hipGraph) and flags (structure validation, light /
 heavy edge split, dense-pull or hybrid traversal direction with lazy
 updates, degree-binned load balancing).  ``diff`` holds the FP32 forward and backward passes
 (og_sssp_f32, og_sssp_backward_f32) and an autograd Function over them;
-``autotune`` searches Delta and the fusion threshold on the device.
+``autotune`` searches the schedule on the device (Delta, update strategy
+and direction, fusion threshold, window, workgroups, degree bins).
 
 Each shortest-path call returns ``(dist, pred, stats)`` with int32 device
 tensors (pred is None when not requested) and a dict of counters.

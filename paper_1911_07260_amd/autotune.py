@@ -13,7 +13,9 @@ is
      SparsePush-DensePull hybrid direction (section 4.2; symmetric graphs);
   2. the fusion threshold and the window size around the best candidate;
   3. Delta refined by factors of sqrt(2) around the best value;
-  4. the workgroup count.
+  4. the workgroup count;
+  5. degree-binned load balancing and its two cut-offs (lane and wavefront
+     bins; eager schedules).
 
 Each stage keeps the best candidate (lowest median engine time).  Results
 are returned as a `Schedule` plus a log of every candidate tried and can be
@@ -29,10 +31,12 @@ from dataclasses import asdict, dataclass, field
 import numpy as np
 import torch
 
-from . import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_TIMING,
-               OG_LAZY_UPDATE, DeviceGraph, Schedule, Workspace, astar_batch, ppsp_batch, sssp, sssp_batch)
+from . import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_DEGREE_BINS, OG_FLAG_DENSE_PULL,
+               OG_FLAG_HYBRID_DIRECTION, OG_FLAG_TIMING, OG_LAZY_UPDATE, DeviceGraph, Schedule, Workspace, astar_batch,
+               ppsp_batch, sssp, sssp_batch)
 
 _DIRECTIONS = OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION
+_CHOSEN = _DIRECTIONS | OG_FLAG_DEGREE_BINS  # flags the search may set
 
 
 @dataclass
@@ -162,5 +166,10 @@ class Autotuner:
         # workgroups
         cands = [best] + [Schedule(**{**asdict(best), "workgroups": w}) for w in (256, 512, 1024)]
         best, best_ms = self._best(cands)
-        best = Schedule(**{**asdict(best), "flags": (base.flags & ~_DIRECTIONS) | (best.flags & _DIRECTIONS)})
+        # degree bins (not with a pull direction)
+        if not best.flags & _DIRECTIONS:
+            cands = [best] + [Schedule(**{**asdict(best), "flags": best.flags | OG_FLAG_DEGREE_BINS, "bin_thread": bt,
+                                          "bin_wave": bw}) for bt in (2, 4) for bw in (16, 64, 256)]
+            best, best_ms = self._best(cands)
+        best = Schedule(**{**asdict(best), "flags": (base.flags & ~_CHOSEN) | (best.flags & _CHOSEN)})
         return TuneResult(best=best, best_ms=best_ms, trials=list(self.trials), seconds=time.perf_counter() - t0)

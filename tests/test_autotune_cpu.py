@@ -2,8 +2,8 @@
 GPU: the runner is a plain function of the schedule)."""
 import math
 
-from paper_1911_07260_amd import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_VALIDATE,
-                                   OG_LAZY_UPDATE, Schedule)
+from paper_1911_07260_amd import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_DEGREE_BINS,
+                                   OG_FLAG_HYBRID_DIRECTION, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, Schedule)
 from paper_1911_07260_amd.autotune import Autotuner
 
 
@@ -55,3 +55,19 @@ def test_lazy_and_direction_candidates():
     # without lazy=True the eager strategies only
     res = Autotuner(runner).tune(weight_scale=15.0)
     assert res.best.update == OG_EAGER_WITH_FUSION and res.best.flags == 0
+
+
+def test_degree_bin_cutoffs():
+    """The last stage times the degree bins at each pair of cut-offs and keeps
+    the best, with its flag."""
+    def runner(s):
+        c = cost(s)
+        if s.flags & OG_FLAG_DEGREE_BINS:
+            c -= 0.5 + (0.5 if (s.bin_thread, s.bin_wave) == (4, 16) else 0.0)
+        return c
+    res = Autotuner(runner, base=Schedule(flags=OG_FLAG_VALIDATE)).tune(weight_scale=15.0)
+    assert res.best.flags == OG_FLAG_VALIDATE | OG_FLAG_DEGREE_BINS
+    assert (res.best.bin_thread, res.best.bin_wave) == (4, 16)
+    # bins that do not pay are left out
+    res = Autotuner(cost).tune(weight_scale=15.0)
+    assert not res.best.flags & OG_FLAG_DEGREE_BINS
