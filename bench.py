@@ -587,6 +587,15 @@ def main() -> int:
                                "gteps": round(bst["reached_edges"] / (bms * 1e-3) / 1e9, 4),
                                "engine_ms": round(bst["engine_ms"], 3), "rounds": bst["rounds"]}
         variants["batched_vs_serial"] = round((wall / args.steps * 1e3) / (bms / nq), 2)
+        # the same batch with degree bins
+        bsched2 = og.Schedule(**{**bsched.__dict__, "flags": TB})
+        og.sssp_batch(dg, bsrcs, bsched2, ws=bws)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, bst2 = og.sssp_batch(dg, bsrcs, bsched2, ws=bws)
+        torch.cuda.synchronize()
+        bms2 = (time.perf_counter() - t) * 1e3
+        variants["batched_degree_bins"] = {"ms_per_query": round(bms2 / nq, 3), "engine_ms": round(bst2["engine_ms"], 3)}
         print(f"[bench] batched {nq} queries: {bms:.1f} ms ({bms / nq:.2f} ms/query)", file=sys.stderr, flush=True)
         del bd, bp, bws
 

@@ -234,6 +234,7 @@ struct Smem {
   int hout;       // light/heavy split
   unsigned hgen;  // light/heavy split
   int pull;       // this round pulls
+  int flat_any;   // degree bins: the batch has rows for the workgroup bin (0 between batches)
 };
 
 // ------------------------------------------------- device-coherent access
@@ -794,11 +795,16 @@ __device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 e
   // the bin is in flight at once.  The batch arrays hold every entry's row
   // start, distance, vertex and offset for all three bins; boff holds the
   // lane bin's degrees (a wavefront-bin entry: minus its degree).
+  const int dflat = in_lane || in_wave ? 0 : deg;
   s.bstart[tid] = start;
   s.boff[tid] = in_lane ? deg : (in_wave ? -deg : 0);
   s.bd[tid] = d;
   s.bv[tid] = v;
   s.bvo[tid] = voff;
+  // whether any row is left to the workgroup bin: set by the wavefronts
+  // that have one before the barrier, read at the workgroup bin, cleared
+  // after the next barrier (nothing writes it in between)
+  if (__ballot(dflat > 0) && lane_id() == 0) s.flat_any = 1;
   __syncthreads();
   {
     const int slots = s.nb * kBinLane;
@@ -852,9 +858,10 @@ __device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 e
   }
 
   // workgroup bin: flat expansion of the remaining rows
-  const int dflat = in_lane || in_wave ? 0 : deg;
+  if (!s.flat_any) return;
   int total;
   const int off = block_excl_scan(dflat, s, &total);  // its barrier also ends the lane bin's use of the arrays
+  if (tid == 0) s.flat_any = 0;  // every lane has read it before that barrier
   if (total == 0) return;
   s.boff[tid] = off;  // row start, distance, vertex and offset are in place from the lane bin
   __syncthreads();
@@ -1888,6 +1895,9 @@ template <class W>
 __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   __shared__ Smem s;
   Counters c;
+  if constexpr (W::kBin) {
+    if (threadIdx.x == 0) s.flat_any = 0;
+  }
   if (threadIdx.x == 0) load_control<W>(a, s);
   __syncthreads();
   while (!s.done) {
@@ -1918,6 +1928,9 @@ template <class W>
 __global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
   __shared__ Smem s;
   Counters c;
+  if constexpr (W::kBin) {
+    if (threadIdx.x == 0) s.flat_any = 0;
+  }
   if (threadIdx.x == 0) load_control<W>(a, s);
   __syncthreads();
   if (s.done) return;
