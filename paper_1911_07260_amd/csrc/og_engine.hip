@@ -744,7 +744,8 @@ __device__ __forceinline__ void finish_edges(const Args& a, Smem& s, Counters& c
 //   - workgroup bin: the remaining rows are expanded over the workgroup by
 //     a block scan and a binary search, as in process_batch.
 template <class W>
-__device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds) {
+__device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 ent, bool from_lds, int nb,
+                                     unsigned new_head, bool advance) {
   const int tid = threadIdx.x;
   const int v = ent.x;
   const int d = ent.y;
@@ -806,8 +807,11 @@ __device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 e
   // after the next barrier (nothing writes it in between)
   if (__ballot(dflat > 0) && lane_id() == 0) s.flat_any = 1;
   __syncthreads();
+  // a batch taken from the ring by every lane alike: its entries are consumed
+  // only now, when every lane has read the ring pointers
+  if (advance && tid == 0) s.lq_head = new_head;
   {
-    const int slots = s.nb * kBinLane;
+    const int slots = nb * kBinLane;
     for (int base = 0; base < slots; base += kBlock) {
       const int e = base + tid;
       const int j = e / kBinLane, k = e % kBinLane;
@@ -865,7 +869,6 @@ __device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 e
   if (total == 0) return;
   s.boff[tid] = off;  // row start, distance, vertex and offset are in place from the lane bin
   __syncthreads();
-  const int nb = s.nb;
   for (int base = 0; base < total; base += kBlock) {
     const int e = base + tid;
     bool has = false;
@@ -1138,7 +1141,6 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
       }
     }
     if constexpr (W::kCore) process_batch_core(a, s, c, ent, mode == 1);
-    else if constexpr (W::kBin) process_batch_binned<W>(a, s, c, ent, mode == 1);
     else process_batch<W>(a, s, c, ent, mode == 1);
     c.batches++;
     c.round_batches++;
@@ -1422,6 +1424,97 @@ __device__ void run_pull(const Args& a, Smem& s, Counters& c) {
       }
     }
     wave_append_buf(a, changed, v);
+  }
+}
+
+// run_round for the degree-binned instantiation.  After the loop's barrier
+// every lane reads the ring pointers; when they call for a batch from the
+// ring (non-empty, below the fusion threshold, no burned reservations),
+// every lane takes the same batch without a second barrier, and the ring's
+// head is advanced after the batch's first barrier.  Any other case takes
+// the decision of thread 0 as in run_round.  The rule reads nothing that
+// thread 0 changes before that decision, except a clamp of the tail that
+// leads every lane to the same (thread-0) branch, so the lanes never take
+// different barrier sequences.
+template <class W>
+__device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
+  const int tid = threadIdx.x;
+  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const unsigned count = s.in_count;
+  const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
+  const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
+  if (tid == 0) {
+    s.lq_head = s.lq_tail = 0;
+    s.exhausted = 0;
+  }
+  for (;;) {
+    // (ring pushes of the previous batch are complete: end-of-batch barrier)
+    __syncthreads();
+    const unsigned h = s.lq_head, t = s.lq_tail;
+    const unsigned lsize = t - h;
+    int mode, nb;
+    unsigned bhead = 0;
+    const bool lane_ring = lsize > 0 && lsize <= (unsigned)kLq && lsize < a.threshold;
+    if (lane_ring) {
+      mode = 1;
+      nb = (int)(lsize < (unsigned)kBlock ? lsize : (unsigned)kBlock);
+      bhead = h;
+    } else {
+      if (tid == 0) {
+        if (s.lq_tail - s.lq_head > (unsigned)kLq) s.lq_tail = s.lq_head + kLq;  // burned reservations
+        const unsigned ls = s.lq_tail - s.lq_head;
+        s.mode = 0;
+        if (ls > 0 && ls >= a.threshold) {
+          s.mode = 3;
+        } else if (ls > 0) {  // not reached: the lanes take such a batch themselves
+          s.mode = 1;
+          s.nb = (int)(ls < (unsigned)kBlock ? ls : (unsigned)kBlock);
+          s.bhead = s.lq_head;
+          s.lq_head += (unsigned)s.nb;
+        } else if (!s.exhausted) {
+          unsigned base;
+          if (fixed) {
+            base = (unsigned)blockIdx.x * per;
+            s.exhausted = 1;
+          } else {
+            base = atomicAdd(&a.ctl->in_head.v, (unsigned)kBlock);
+          }
+          if (base < count) {
+            s.mode = 2;
+            const unsigned left = count - base;
+            s.nb = (int)(left < per ? left : per);
+            s.gbase = base;
+          } else {
+            s.exhausted = 1;
+          }
+        }
+      }
+      __syncthreads();
+      mode = s.mode;
+      nb = s.nb;
+      bhead = s.bhead;
+    }
+    if (mode == 0) break;
+    if (mode == 3) {
+      publish_local(a, s, c);
+      continue;
+    }
+    if (a.tgts) {
+      for (int q = tid; q < a.reps; q += kBlock) s.tb[q] = a.dist[a.tgts[q]];
+      __syncthreads();
+    }
+    int4 ent = make_int4(-1, 0, 0, 0);
+    if (tid < nb) {
+      if (mode == 1) {
+        ent = s.lq[(bhead + tid) & (kLq - 1)];
+      } else {
+        const int2 e = ld_entry(in, (size_t)s.gbase + tid);
+        ent = make_int4(e.x, e.y, 0, 0);
+      }
+    }
+    process_batch_binned<W>(a, s, c, ent, mode == 1, nb, bhead + (unsigned)nb, lane_ring);
+    c.batches++;
+    c.round_batches++;
   }
 }
 
@@ -1905,6 +1998,8 @@ __global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
       run_mark<W>(a, s, c);
       round_barrier<W>(a, s, c, true, false);
       run_pull<W>(a, s, c);
+    } else if constexpr (W::kBin) {
+      run_round_binned<W>(a, s, c);
     } else {
       run_round<W>(a, s, c);
     }
@@ -1949,7 +2044,8 @@ __global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
     return;
   }
   if (phase == 0) {
-    run_round<W>(a, s, c);
+    if constexpr (W::kBin) run_round_binned<W>(a, s, c);
+    else run_round<W>(a, s, c);
     round_barrier<W>(a, s, c, false, !a.lazy);
   } else {
     run_flush<W>(a, s, c);
