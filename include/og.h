@@ -113,6 +113,15 @@ typedef int32_t og_status;
                                mean degree, exceed m/20) and pushes otherwise.
                                Same requirements; not together with
                                OG_FLAG_DENSE_PULL.                            */
+#define OG_FLAG_KEEP_SPLIT 128u /* with OG_FLAG_LIGHT_HEAVY: reuse the split
+                               copy of the rows that the previous split call on
+                               this workspace built, when it was for the same
+                               graph arrays, sizes and Delta (the library keeps
+                               a record per workspace; any other call on the
+                               workspace drops it, and a mismatch rebuilds).
+                               The caller promises that the graph's contents
+                               have not changed since.  Ignored without
+                               OG_FLAG_LIGHT_HEAVY.                           */
 #define OG_FLAG_DEGREE_BINS 64u /* degree-binned load balancing: within each
                                batch of queue entries, a vertex of at most
                                schedule.bin_thread edges gets a fixed group of

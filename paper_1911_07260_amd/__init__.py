@@ -36,7 +36,7 @@ from . import _lib
 from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_GRAPH_ROUNDS, OG_ENGINE_HOST_ROUNDS,
                    OG_ENGINE_PERSISTENT, OG_ERR_HIP, OG_ERR_INTERNAL, OG_ERR_INVALID_ARG, OG_ERR_NEGATIVE_WEIGHT,
                    OG_ERR_OVERFLOW, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE, OG_FLAG_ASYNC, OG_FLAG_DEGREE_BINS,
-                   OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_LIGHT_HEAVY, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, OG_OK,
+                   OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_KEEP_SPLIT, OG_FLAG_LIGHT_HEAVY, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, OG_OK,
                    OgError, OgGraph, OgSchedule, OgStats)
 
 INF = 2**31 - 1

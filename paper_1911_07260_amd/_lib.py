@@ -28,6 +28,7 @@ OG_FLAG_LIGHT_HEAVY = 8
 OG_FLAG_DENSE_PULL = 16
 OG_FLAG_HYBRID_DIRECTION = 32
 OG_FLAG_DEGREE_BINS = 64
+OG_FLAG_KEEP_SPLIT = 128
 
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1

@@ -2254,6 +2254,48 @@ int pow2_at_least(int x) {
   return p;
 }
 
+// Split copies of the rows held by workspaces (light/heavy split): the
+// workspace, the graph's arrays and sizes, Delta and where the copy lies.
+// A split call records what it built; every other call on a workspace
+// forgets it, since its layout may cover the copy.  With OG_FLAG_KEEP_SPLIT
+// a split call whose record matches reuses the copy instead of rebuilding.
+struct SplitKey {
+  const void* ws;
+  const void* row_ptr;
+  const void* col;
+  const void* w;
+  long long n, m;
+  unsigned delta;
+  const void* copy;
+  bool operator==(const SplitKey& o) const {
+    return ws == o.ws && row_ptr == o.row_ptr && col == o.col && w == o.w && n == o.n && m == o.m &&
+           delta == o.delta && copy == o.copy;
+  }
+};
+std::mutex g_split_mu;
+std::vector<SplitKey> g_split_keys;
+
+void forget_split(const void* ws) {
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  g_split_keys.erase(std::remove_if(g_split_keys.begin(), g_split_keys.end(),
+                                    [&](const SplitKey& k) { return k.ws == ws; }),
+                     g_split_keys.end());
+}
+
+bool split_kept(const SplitKey& key) {
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  return std::find(g_split_keys.begin(), g_split_keys.end(), key) != g_split_keys.end();
+}
+
+void record_split(const SplitKey& key) {
+  std::lock_guard<std::mutex> lk(g_split_mu);
+  g_split_keys.erase(std::remove_if(g_split_keys.begin(), g_split_keys.end(),
+                                    [&](const SplitKey& k) { return k.ws == key.ws; }),
+                     g_split_keys.end());
+  if (g_split_keys.size() >= 64) g_split_keys.erase(g_split_keys.begin());
+  g_split_keys.push_back(key);
+}
+
 // Per-thread HIP events for OG_FLAG_TIMING (created on first use).
 struct Timers {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -2343,7 +2385,7 @@ bool schedule_ok(const og_schedule* s) {
     return false;
   if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
   if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL |
-                   OG_FLAG_HYBRID_DIRECTION | OG_FLAG_DEGREE_BINS))
+                   OG_FLAG_HYBRID_DIRECTION | OG_FLAG_DEGREE_BINS | OG_FLAG_KEEP_SPLIT))
     return false;
   if (s->bin_thread < 0 || s->bin_wave < 0) return false;
   // degree bins are their own instantiation: not with the split or a pull direction
@@ -2463,6 +2505,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   og_schedule r = resolved(sched);
   if (force_delta1) r.delta = 1;
   if (ws_size < ws_bytes_for(g, &r, sh)) return fail(OG_ERR_WORKSPACE);
+
   hipStream_t stream = (hipStream_t)stream_v;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(OG_ERR_HIP);
@@ -2572,6 +2615,16 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     }
   }
 
+  // Before anything is launched: this call's layout may cover a split copy
+  // held in the workspace, unless it is the same copy, kept on request.
+  SplitKey split_key{};
+  bool keep_split = false;
+  if constexpr (W::kSplit) {
+    split_key = SplitKey{ws, g->row_ptr, g->col, g->w, (long long)g->n, g->m, a.delta, split_col};
+    keep_split = (r.flags & OG_FLAG_KEEP_SPLIT) && split_kept(split_key);
+  }
+  if (!keep_split) forget_split(ws);
+
   const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
   if (timing) (void)hipEventRecord(t_timers.ev[0], stream);
   // query table: sources then targets, carried in kernel arguments
@@ -2630,10 +2683,16 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   if constexpr (W::kPull)  // reads the rows: after their validation
     hipLaunchKernelGGL(k_pull_slices, dim3(fill_grid), dim3(kBlock), 0, stream, a, pull_slices);
   if constexpr (W::kSplit) {
-    hipLaunchKernelGGL(k_split_small, dim3(fill_grid), dim3(kBlock), 0, stream, a, split_col, split_w, split_l,
-                       split_big);
-    hipLaunchKernelGGL(k_split_big, dim3(fill_grid), dim3(kBlock), 0, stream, a, split_col, split_w, split_l,
-                       split_big);
+    if (keep_split) {
+      // the copy is in place: only the per-call heavy-list stamps are cleared
+      hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, (int*)a.hmark, (long long)a.n, 0);
+    } else {
+      hipLaunchKernelGGL(k_split_small, dim3(fill_grid), dim3(kBlock), 0, stream, a, split_col, split_w, split_l,
+                         split_big);
+      hipLaunchKernelGGL(k_split_big, dim3(fill_grid), dim3(kBlock), 0, stream, a, split_col, split_w, split_l,
+                         split_big);
+      record_split(split_key);
+    }
   }
   if (timing) (void)hipEventRecord(t_timers.ev[1], stream);
 
@@ -2888,6 +2947,7 @@ og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const
   og::DeviceInfo di;
   if (hipGetDevice(&dev) != hipSuccess || !og::device_info(dev, &di)) return OG_ERR_HIP;
   hipStream_t st = (hipStream_t)stream;
+  og::forget_split(ws);  // the workspace may have held a split copy
   double* acc = (double*)ws;
   int* kids = (int*)((char*)ws + sizeof(double) * (size_t)g->n);
   int* pending = kids + g->n;

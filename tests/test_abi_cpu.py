@@ -109,7 +109,7 @@ def test_workspace_bytes():
 
 @pytest.mark.parametrize("field,value", [
     ("delta", 0), ("update", 3), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
-    ("max_rounds", -1), ("flags", 128), ("fusion_threshold", -2),
+    ("max_rounds", -1), ("flags", 256), ("fusion_threshold", -2),
     # a pull direction needs lazy updates, and takes one direction flag
     ("flags", 16), ("flags", 32),
     # degree bins: non-negative cut-offs, not with the split or a pull direction

@@ -129,3 +129,38 @@ def test_split_rmat20(orc):
     d, p, st = og.sssp(dg, src, og.Schedule(delta=32, update=og.OG_EAGER_NO_FUSION, flags=LH))
     torch.cuda.synchronize()
     check(orc, g, src, d, p, "split rmat20")
+
+
+def test_split_copy_kept_across_calls(orc, graphs):
+    """OG_FLAG_KEEP_SPLIT reuses the split copy of the previous split call on
+    the same workspace, graph and Delta, and rebuilds it whenever one of them
+    changed or another call used the workspace in between; every result must
+    still be the oracle's."""
+    g, dg = graphs["rmat"]
+    rg, rdg = graphs["road"]
+    ws = og.Workspace(DEV)
+    keep = LH | og.OG_FLAG_KEEP_SPLIT
+    srcs = [int(x) for x in gg.pick_sources(g, 3, seed=35)]
+    rsrc = int(gg.pick_sources(rg, 1, seed=36)[0])
+    w2 = gg.with_weights(g, g.w % 50 + 1)
+    dg2 = og.DeviceGraph.from_host(w2, DEV)
+    steps = [
+        ("build", dg, g, srcs[0], 64, keep),
+        ("reuse", dg, g, srcs[1], 64, keep),
+        ("reuse again", dg, g, srcs[2], 64, keep),
+        ("other delta: rebuild", dg, g, srcs[0], 16, keep),
+        ("back to 64: rebuild", dg, g, srcs[1], 64, keep),
+        ("plain call on the workspace", dg, g, srcs[2], 64, 0),
+        ("after it: rebuild", dg, g, srcs[0], 64, keep),
+        ("other graph of the same shape: rebuild", dg2, w2, srcs[1], 64, keep),
+        ("road graph: rebuild", rdg, rg, rsrc, 512, keep),
+        ("road reuse", rdg, rg, rsrc, 512, keep),
+        ("split without keep: rebuild", dg, g, srcs[2], 64, LH),
+        ("reuse after it", dg, g, srcs[0], 64, keep),
+    ]
+    for tag, dgx, gx, src, delta, flags in steps:
+        say(f"keep split: {tag}")
+        d, p, st = og.sssp(dgx, src, og.Schedule(delta=delta, update=og.OG_EAGER_NO_FUSION, flags=flags), ws=ws)
+        torch.cuda.synchronize()
+        assert st["status"] == 0
+        check(orc, gx, src, d, p, f"keep split: {tag}")
