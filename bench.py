@@ -453,7 +453,7 @@ def main() -> int:
     ap.add_argument("--pairs", type=int, default=4096)
     ap.add_argument("--astar-delta", type=int, default=512)
     ap.add_argument("--graphs", type=int, default=1024)
-    ap.add_argument("--rgg-delta", type=int, default=4096)
+    ap.add_argument("--rgg-delta", type=int, default=131072)
     args = ap.parse_args()
     if args.summarize_rocpd:
         return summarize_rocpd(args.summarize_rocpd, args.counter)
