@@ -308,13 +308,15 @@ def workload_diff(args) -> int:
     import paper_1911_07260_amd as og
     dev = torch.device("cuda:0")
     res = {}
-    for name, g, delta in (("road2048", gg.road(2048, seed=0), 4096), ("rmat22", gg.rmat(22, 16, seed=0), 64)):
+    # degree bins on the road graph (faster there), flat expansion on R-MAT
+    for name, g, delta, lb in (("road2048", gg.road(2048, seed=0), 4096, og.OG_FLAG_DEGREE_BINS),
+                               ("rmat22", gg.rmat(22, 16, seed=0), 64, 0)):
         w = gg.float_weights(g, 1.0, 1000.0, seed=3)
         dg = og.DeviceGraph.from_host(g, dev)
         wt = torch.from_numpy(w).to(dev).requires_grad_(True)
         s = int(gg.pick_sources(g, 1, seed=1)[0])
         tg = torch.from_numpy(gg.pick_sources(g, 1024, seed=3)).to(dev)
-        sched = og.Schedule(delta=delta, flags=og.OG_FLAG_TIMING)
+        sched = og.Schedule(delta=delta, flags=og.OG_FLAG_TIMING | lb)
         times = []
         for it in range(4):
             wt.grad = None
@@ -331,6 +333,16 @@ def workload_diff(args) -> int:
             if it:
                 times.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3))
         fw, bw = np.mean([t[0] for t in times]), np.mean([t[1] for t in times])
+        # the forward pass alone with the other load balancing
+        sb = og.Schedule(delta=delta, flags=og.OG_FLAG_TIMING | (lb ^ og.OG_FLAG_DEGREE_BINS))
+        fwb = []
+        for it in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            og.sssp_f32(dg, wt.detach(), s, sb)
+            torch.cuda.synchronize()
+            if it:
+                fwb.append((time.perf_counter() - t0) * 1e3)
         parity = None
         if not args.no_cpu:
             import oracle
@@ -341,7 +353,10 @@ def workload_diff(args) -> int:
             rel = float(np.max(np.abs(dn[fin] - ref[fin]) / ref[fin]))
             parity = {"forward_max_rel_err_vs_f64": rel}
         res[name] = {"n": g.n, "m": g.m, "delta": delta, "forward_ms": round(float(fw), 3),
-                     "backward_ms": round(float(bw), 3), "parity": parity}
+                     "backward_ms": round(float(bw), 3),
+                     "load_balance": "degree bins" if lb else "flat expansion",
+                     ("forward_flat_ms" if lb else "forward_degree_bins_ms"): round(float(np.mean(fwb)), 3),
+                     "parity": parity}
         print(f"[bench] diff {name}: forward {fw:.2f} ms backward {bw:.2f} ms", file=sys.stderr, flush=True)
         del dg, wt, dist
     r = res["road2048"]

@@ -130,10 +130,10 @@ typedef int32_t og_status;
                                wavefront, 64 edges at a time, and larger ones
                                the whole workgroup (a block scan spreads their
                                edges over all lanes, the default for every
-                               vertex without this flag).  int32 weights
-                               (og_sssp_f32 returns OG_ERR_INVALID_ARG); not
-                               together with OG_FLAG_LIGHT_HEAVY or a pull
-                               direction; og_kcore ignores it.               */
+                               vertex without this flag).  int32 and float32
+                               weights (og_sssp_f32); not together with
+                               OG_FLAG_LIGHT_HEAVY or a pull direction;
+                               og_kcore ignores it.                           */
 
 /* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
 #define OG_EAGER_NO_FUSION 0

@@ -382,6 +382,9 @@ struct CorePullW : CoreW {
 struct BinW : IntW {
   static constexpr bool kBin = true;
 };
+struct BinFloatW : FloatW {
+  static constexpr bool kBin = true;
+};
 
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
   int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
@@ -2213,6 +2216,7 @@ struct DeviceInfo {
   int occ_pull = 0;   // co-resident k_persistent<PullW> workgroups per CU
   int occ_core_pull = 0;  // co-resident k_persistent<CorePullW> workgroups per CU
   int occ_bin = 0;    // co-resident k_persistent<BinW> workgroups per CU
+  int occ_bin_float = 0;  // co-resident k_persistent<BinFloatW> workgroups per CU
   int coop = 0;
   bool valid = false;
 };
@@ -2241,6 +2245,9 @@ bool device_info(int dev, DeviceInfo* out) {
         hipSuccess)
       return false;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_bin, k_persistent<BinW>, kBlock, 0) != hipSuccess)
+      return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_bin_float, k_persistent<BinFloatW>, kBlock, 0) !=
+        hipSuccess)
       return false;
     di.valid = true;
   }
@@ -2519,6 +2526,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
                   : std::is_same<W, PullW>::value     ? di.occ_pull
                   : std::is_same<W, CorePullW>::value ? di.occ_core_pull
                   : std::is_same<W, BinW>::value      ? di.occ_bin
+                  : std::is_same<W, BinFloatW>::value ? di.occ_bin_float
                                                       : di.occ_int;
   int maxwg = di.cus * (occ > 0 ? occ : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
@@ -2806,7 +2814,8 @@ og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, cons
   if (s->flags & OG_FLAG_DEGREE_BINS) {
     if constexpr (std::is_same<W, IntW>::value)
       return run<BinW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
-    return fail(OG_ERR_INVALID_ARG);  // int32 weights only
+    else
+      return run<BinFloatW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
   }
   return run<W>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
 }

@@ -37,15 +37,16 @@ def case(kind):
     return g, w
 
 
+@pytest.mark.parametrize("flags", [0, og.OG_FLAG_DEGREE_BINS])
 @pytest.mark.parametrize("kind", ["grid", "road", "rmat"])
 @pytest.mark.parametrize("delta,update", [(512, 1), (4096, 1), (512, 0), (1 << 16, 1)])
-def test_forward_bit_exact_vs_f32_oracle(orc, kind, delta, update):
+def test_forward_bit_exact_vs_f32_oracle(orc, kind, delta, update, flags):
     g, w = case(kind)
     dg = og.DeviceGraph.from_host(g, DEV)
     wt = torch.from_numpy(w).to(DEV)
     s = int(gg.pick_sources(g, 1, seed=4)[0])
-    say(f"f32 forward {kind} delta={delta} update={update}")
-    d, p, pe, st = og.sssp_f32(dg, wt, s, og.Schedule(delta=delta, update=update))
+    say(f"f32 forward {kind} delta={delta} update={update} flags={flags}")
+    d, p, pe, st = og.sssp_f32(dg, wt, s, og.Schedule(delta=delta, update=update, flags=flags))
     torch.cuda.synchronize()
     d, p, pe = d.cpu().numpy(), p.cpu().numpy(), pe.cpu().numpy()
     ref = orc.dijkstra_real(g, w, s, f32=True)
