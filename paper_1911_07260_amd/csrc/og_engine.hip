@@ -2375,7 +2375,8 @@ size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   // light/heavy split: col and w copies, light counts, long-row list, bucket
   // stamps and two heavy lists of (v, 0) entries
   if (split_on(r, sh)) b += 2 * vec_bytes(g->m) + 2 * vec_bytes(g->n) + vec_bytes(nv) + 4 * vec_bytes(nv);
-  // pull direction: frontier bitmap and the long rows' slices
+  // pull direction: frontier marks ((stamp, distance) pairs; k-core: a
+  // bitmap) and the long rows' slices
   if (pull_mode(r) != kPullNever)
     b += (sh.core ? vec_bytes((nv + 31) / 32) : vec_bytes(2 * nv)) + vec_bytes(2 * (long long)slice_cap(g->m));
   return b;

@@ -359,8 +359,9 @@ def test_graph_rounds_replayed(orc, road256, cfg0):
 @pytest.mark.slow
 @pytest.mark.parametrize("delta", [512, 1024, 1 << 13])
 def test_road_full_size_one_source(orc, delta):
-    """Full 4096^2 road-like grid; Delta 512 fused persistent is the
-    benchmark's launch configuration: bit-exact."""
+    """Full 4096^2 road-like grid, fused, persistent engine, flat expansion
+    (at Delta 512 the benchmark's fused_flat leg; its headline schedule adds
+    degree bins, checked at full size with the bins' tests): bit-exact."""
     g = gg.road(4096, seed=0)
     dg = og.DeviceGraph.from_host(g, DEV)
     src = int(gg.pick_sources(g, 1, seed=1)[0])

@@ -131,6 +131,27 @@ def test_split_rmat20(orc):
     check(orc, g, src, d, p, "split rmat20")
 
 
+@pytest.mark.slow
+def test_split_rmat24_kept_full_size(orc):
+    """The R-MAT benchmark line's schedule at its full size: R-MAT scale 24,
+    the benchmark's first two sources, Delta 64, unfused, light/heavy split
+    with the copy kept (the first call builds it, the second reuses it):
+    distances and predecessors bit-exact."""
+    say("rmat24: generating")
+    g = gg.rmat(24, 16, seed=0)
+    dg = og.DeviceGraph.from_host(g, DEV)
+    ws = og.Workspace(DEV)
+    srcs = [int(x) for x in gg.pick_sources(g, 4, seed=2)][:2]
+    for i, src in enumerate(srcs):
+        say(f"split rmat24 src={src} delta=64 unfused kept ({'build' if i == 0 else 'reuse'})")
+        d, p, st = og.sssp(dg, src, og.Schedule(delta=64, update=og.OG_EAGER_NO_FUSION,
+                                                flags=LH | og.OG_FLAG_KEEP_SPLIT), ws=ws)
+        torch.cuda.synchronize()
+        assert st["status"] == 0
+        say(f"split rmat24 src={src}: oracle")
+        check(orc, g, src, d, p, f"split rmat24 src={src}")
+
+
 def test_split_copy_kept_across_calls(orc, graphs):
     """OG_FLAG_KEEP_SPLIT reuses the split copy of the previous split call on
     the same workspace, graph and Delta, and rebuilds it whenever one of them
