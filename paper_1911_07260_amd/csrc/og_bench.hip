@@ -12,6 +12,8 @@
 //            [--engine persistent|host|graph] [--window K] [--kcore]
 //            [--direction push|pull|hybrid]   (pull and hybrid need --update lazy)
 //            [--bins]   (degree-binned load balancing)
+//            [--split [--keep]]   (light/heavy edge split; --keep reuses the
+//                                  split copy across the calls)
 //            [--copy-calibration]
 //
 // --copy-calibration instead runs a plain copy kernel over 1 GiB three
@@ -78,7 +80,7 @@ int main(int argc, char** argv) {
   int update = OG_EAGER_WITH_FUSION, engine = OG_ENGINE_PERSISTENT;
   bool rmat = false, kcore = false;
   uint32_t direction = 0;
-  bool bins = false;
+  bool bins = false, split = false, keep = false;
   for (int i = 1; i < argc; ++i) {
     auto next = [&](void) -> const char* {
       if (i + 1 >= argc) { std::fprintf(stderr, "missing value for %s\n", argv[i]); std::exit(2); }
@@ -108,6 +110,8 @@ int main(int argc, char** argv) {
       direction = !std::strcmp(d, "pull") ? OG_FLAG_DENSE_PULL : !std::strcmp(d, "hybrid") ? OG_FLAG_HYBRID_DIRECTION : 0u;
     }
     else if (!std::strcmp(argv[i], "--bins")) bins = true;
+    else if (!std::strcmp(argv[i], "--split")) split = true;
+    else if (!std::strcmp(argv[i], "--keep")) keep = true;
     else if (!std::strcmp(argv[i], "--copy-calibration")) return copy_calibration();
     else { std::fprintf(stderr, "unknown argument %s\n", argv[i]); return 2; }
   }
@@ -147,7 +151,8 @@ int main(int argc, char** argv) {
   s.delta = delta;
   s.update = update;
   s.engine = engine;
-  s.flags = OG_FLAG_TIMING | direction | (bins ? OG_FLAG_DEGREE_BINS : 0u);
+  s.flags = OG_FLAG_TIMING | direction | (bins ? OG_FLAG_DEGREE_BINS : 0u) | (split ? OG_FLAG_LIGHT_HEAVY : 0u) |
+            (split && keep ? OG_FLAG_KEEP_SPLIT : 0u);
   if (window > 0) s.window_buckets = window;
   const size_t wsb = kcore ? og_workspace_bytes_kcore(&g, &s) : og_workspace_bytes(&g, &s);
   void* ws = nullptr;
