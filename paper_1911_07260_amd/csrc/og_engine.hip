@@ -101,6 +101,18 @@ constexpr int kSlice = 2048;
 __host__ __device__ inline unsigned long long slice_cap(long long m) {
   return (unsigned long long)(m / kSlice + m / kLongRow + 1);
 }
+// The predecessor pass leaves rows longer than kPredLong edges out of its
+// per-wavefront vertex chunks and hands them out in slices of kPredSlice
+// edges, so that a hub's row does not keep one wavefront busy long after
+// the rest.  Slices per copy of the graph: at most m / kPredSlice + m /
+// kPredLong + 1.
+constexpr int kPredLong = 1024;
+constexpr int kPredSlice = 2048;
+constexpr int kPredIlp = 4;  // groups of 64 edges whose loads a wavefront keeps in flight
+constexpr int kPredParDeg = 8;  // mean degree from which the parity filter is used
+__host__ __device__ inline unsigned long long pred_slice_cap(long long m, int reps) {
+  return (unsigned long long)reps * (unsigned long long)(m / kPredSlice + m / kPredLong + 1);
+}
 // Light/heavy split: LDS ring entries carry a vertex's light-edge count with
 // this bit set when the vertex also has heavy edges.
 constexpr int kHeavyBit = 1 << 30;
@@ -160,6 +172,7 @@ struct Ctl {
   Word big_rows;       // light/heavy split: rows left to the wavefront split pass
   Word64 sym;          // symmetry checksum of OG_FLAG_VALIDATE with a pull direction
   Word slices;         // pull direction: row slices listed per copy of the graph
+  Word64 pred_slices;  // predecessor pass: slices of long rows listed
 };
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block too large");
 
@@ -303,6 +316,8 @@ struct IntW {
     return true;
   }
   __device__ static bool tight(int du, int wraw, int dv) { return (unsigned)du + (unsigned)wraw == (unsigned)dv; }
+  // the bit pattern dist[v] has when the edge is tight
+  __device__ static unsigned cand(int du, int wraw) { return (unsigned)du + (unsigned)wraw; }
   // priority of vertex v at distance d: d, or d + h[v] for A*
   __device__ static unsigned key(const Args& a, int v, int d) {
     return a.h ? (unsigned)d + (unsigned)a.h[v] : (unsigned)d;  // both < 2^31: no wrap
@@ -334,6 +349,11 @@ struct FloatW {
   }
   __device__ static bool tight(int du, int wraw, int dv) {
     return __fadd_rn(__int_as_float(du), __int_as_float(wraw)) == __int_as_float(dv);
+  }
+  // the bit pattern dist[v] has when the edge is tight (distances are never
+  // -0, so equal values have equal bits)
+  __device__ static unsigned cand(int du, int wraw) {
+    return (unsigned)__float_as_int(__fadd_rn(__int_as_float(du), __int_as_float(wraw)));
   }
   __device__ static unsigned key(const Args&, int, int d) { return (unsigned)d; }
   // floor(d / Delta): the float64 quotient of two float32 values never
@@ -2065,12 +2085,35 @@ __global__ __launch_bounds__(kBlock) void k_fill(int* p, long long n, int value)
 // Canonical predecessors: for every edge (u,v) of every query copy with
 // dist[u] finite and dist[u] + w == dist[v], pred[v] = min(pred[v], u) (base
 // vertex ids).  One wavefront per chunk of 64 consecutive source vertices of
-// one copy walks the chunk's contiguous edge range with coalesced loads;
-// each edge finds its source lane by a binary search over the lanes' row
-// offsets.  Also counts reached vertices and edges.  pred == nullptr:
-// counts only.
-template <class W>
-__global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
+// one copy: a wavefront scan numbers the chunk's edges, which the lanes then
+// take 64 at a time, each finding its source lane by a binary search over
+// the lanes' offsets; the edge loads of consecutive lanes are contiguous
+// within a row.  When longs is given, a row longer than kPredLong edges is
+// left out and listed instead as slices of kPredSlice edges (at most lcap
+// entries) for k_pred_long.  With the parity summary sum, edges that cannot
+// be tight by parity skip their dist read.  Also counts reached vertices and
+// edges.  pred == nullptr: counts only.
+// Parity summary of the final distances for the predecessor pass: bit
+// v % 64 of word v / 64 is the lowest bit of dist[v]'s bit pattern (one bit
+// per vertex, 32 times smaller than dist).
+__global__ __launch_bounds__(kBlock) void k_pred_summary(Args a, unsigned long long* sum) {
+  const long long nv = a.n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < nv; base += stride) {
+    const long long v = base + threadIdx.x;
+    const unsigned long long word = __ballot(v < nv && (a.dist[v] & 1));
+    if (lane_id() == 0 && v < nv) sum[v >> 6] = word;
+  }
+}
+// Whether the summary allows dist[u] to equal the would-be distance c: an
+// edge whose c has the other parity is not tight, and its random dist read
+// is saved.
+__device__ __forceinline__ bool par_ok(const unsigned long long* sum, long long u, unsigned c) {
+  return ((unsigned)(sum[u >> 6] >> (u & 63)) & 1u) == (c & 1u);
+}
+template <class W, bool kPar>
+__global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred, int2* longs, unsigned long long lcap,
+                                                       const unsigned long long* sum) {
   const int lane = (int)lane_id();
   const long long nwave = (long long)gridDim.x * (kBlock / kWave);
   const long long per_copy = ((long long)a.nbase + kWave - 1) / kWave;
@@ -2081,30 +2124,74 @@ __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
     const long long voff = q * a.nbase;
     const long long v0 = (ch - q * per_copy) * kWave;
     const long long v = v0 + lane;
-    const long long vend = v0 + kWave < a.nbase ? v0 + kWave : a.nbase;
     const long long e0 = a.row_ptr[v0];
-    const long long e1 = a.row_ptr[vend];
-    const int rs = v < a.nbase ? (int)(a.row_ptr[v] - e0) : (int)(e1 - e0);
+    long long r0 = e0, r1 = e0;
+    if (v < a.nbase) {
+      r0 = a.row_ptr[v];
+      r1 = a.row_ptr[v + 1];
+    }
     const int dv = v < a.nbase ? a.dist[voff + v] : W::kInfBits;
+    const int deg = (int)(r1 - r0);
     if (v < a.nbase && dv != W::kInfBits) {
       rv++;
-      re += (unsigned long long)(a.row_ptr[v + 1] - a.row_ptr[v]);
+      re += (unsigned long long)deg;
     }
     if (!pred) continue;
-    for (long long base = e0; base < e1; base += kWave) {
-      const long long e = base + lane;
-      const int rel = (int)(e - e0);
-      int lo = 0;
+    const bool live = dv != W::kInfBits && deg > 0;
+    const bool is_long = live && longs && deg > kPredLong;
+    if (is_long) {  // its edges go to k_pred_long
+      const unsigned nsl = (unsigned)((deg + kPredSlice - 1) / kPredSlice);
+      const unsigned long long at = atomicAdd(&a.ctl->pred_slices.v, (unsigned long long)nsl);
+      if (at + nsl <= lcap) {
+        for (unsigned k = 0; k < nsl; ++k) longs[at + k] = make_int2((int)(voff + v), (int)k);
+      } else {
+        set_status(a.ctl, OG_ERR_INTERNAL);
+      }
+    }
+    const int eff = live && !is_long ? deg : 0;
+    int inc = eff;  // inclusive scan of eff over the wavefront
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int r = __shfl(rs, lo + step);
-        if (r <= rel) lo += step;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int t = __shfl_up(inc, o);
+      if (lane >= o) inc += t;
+    }
+    const int total = __shfl(inc, kWave - 1);
+    const int off = inc - eff;
+    const int rel = (int)(r0 - e0);
+    // kPredIlp groups of 64 edges per step, their loads in flight together
+    for (int k0 = 0; k0 < total; k0 += kPredIlp * kWave) {
+      int cj[kPredIlp], du[kPredIlp], wt[kPredIlp], dd[kPredIlp], src[kPredIlp];
+      bool ok[kPredIlp];
+#pragma unroll
+      for (int j = 0; j < kPredIlp; ++j) {  // edge loads of every group
+        const int k = k0 + j * kWave + lane;
+        int lo = 0;  // the last lane whose offset is <= k: it owns edge k
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const int o2 = __shfl(off, lo + step);
+          if (o2 <= k) lo += step;
+        }
+        du[j] = __shfl(dv, lo);
+        const int rj = __shfl(rel, lo);
+        const int oj = __shfl(off, lo);
+        src[j] = lo;
+        ok[j] = k < total;
+        cj[j] = 0;
+        wt[j] = 0;
+        if (ok[j]) {
+          const long long e = e0 + rj + (k - oj);
+          cj[j] = a.col[e];
+          wt[j] = a.w[e];
+        }
       }
-      const int du = __shfl(dv, lo);
-      if (e < e1 && du != W::kInfBits) {
-        const long long u = voff + a.col[e];
-        if (W::tight(du, a.w[e], a.dist[u])) atomicMin(&pred[u], (int)(v0 + lo));
+#pragma unroll
+      for (int j = 0; j < kPredIlp; ++j) {
+        if constexpr (kPar) ok[j] = ok[j] && par_ok(sum, voff + cj[j], W::cand(du[j], wt[j]));
+        dd[j] = ok[j] ? a.dist[voff + cj[j]] : 0;
       }
+#pragma unroll
+      for (int j = 0; j < kPredIlp; ++j)
+        if (ok[j] && W::tight(du[j], wt[j], dd[j])) atomicMin(&pred[voff + cj[j]], (int)(v0 + src[j]));
     }
   }
   for (int o = 32; o >= 1; o >>= 1) {
@@ -2114,6 +2201,53 @@ __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred) {
   if (lane == 0) {
     if (rv) atomicAdd(&a.ctl->st[kStReachedV].v, rv);
     if (re) atomicAdd(&a.ctl->st[kStReachedE].v, re);
+  }
+}
+
+// The long rows listed by k_pred_edges: one wavefront per slice of
+// kPredSlice edges, the same test per edge.
+template <class W, bool kPar>
+__global__ __launch_bounds__(kBlock) void k_pred_long(Args a, int* pred, const int2* longs, unsigned long long lcap,
+                                                      const unsigned long long* sum) {
+  // more than lcap slices only for a malformed graph: the call then ends
+  // with OG_ERR_INTERNAL and the list is not read
+  const unsigned long long count =
+      __hip_atomic_load(&a.ctl->pred_slices.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (count > lcap) return;
+  const int lane = (int)lane_id();
+  const long long nwave = (long long)gridDim.x * (kBlock / kWave);
+  for (long long i = (long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < (long long)count;
+       i += nwave) {
+    const int2 ent = longs[i];
+    const int vb = a.reps == 1 ? ent.x : (int)((unsigned)ent.x % (unsigned)a.nbase);
+    const long long voff = (long long)ent.x - vb;
+    const long long r1 = a.row_ptr[vb + 1];
+    const long long s0 = a.row_ptr[vb] + (long long)ent.y * kPredSlice;
+    const long long s1 = s0 + kPredSlice < r1 ? s0 + kPredSlice : r1;
+    const int du = a.dist[ent.x];
+    for (long long eb = s0; eb < s1; eb += kPredIlp * kWave) {
+      int cj[kPredIlp], wt[kPredIlp], dd[kPredIlp];
+      bool ok[kPredIlp];
+#pragma unroll
+      for (int j = 0; j < kPredIlp; ++j) {
+        const long long e = eb + j * kWave + lane;
+        ok[j] = e < s1;
+        cj[j] = 0;
+        wt[j] = 0;
+        if (ok[j]) {
+          cj[j] = a.col[e];
+          wt[j] = a.w[e];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kPredIlp; ++j) {
+        if constexpr (kPar) ok[j] = ok[j] && par_ok(sum, voff + cj[j], W::cand(du, wt[j]));
+        dd[j] = ok[j] ? a.dist[voff + cj[j]] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < kPredIlp; ++j)
+        if (ok[j] && W::tight(du, wt[j], dd[j])) atomicMin(&pred[voff + cj[j]], vb);
+    }
   }
 }
 
@@ -2742,15 +2876,48 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   }
   if (timing) (void)hipEventRecord(t_timers.ev[2], stream);
   if constexpr (W::kCore) {
-    if (stats) hipLaunchKernelGGL(k_pred_edges<IntW>, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
+    if (stats)
+      hipLaunchKernelGGL((k_pred_edges<IntW, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr,
+                         (int2*)nullptr, 0ull, (const unsigned long long*)nullptr);
   } else if (pred) {
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n, kInf);
-    hipLaunchKernelGGL(k_pred_edges<W>, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred);
+    // the long rows' slice list and the parity summary go where the queues
+    // were (unused once the engine is done), when they are large enough;
+    // otherwise every row stays in its chunk and every edge reads dist
+    const unsigned long long lcap = pred_slice_cap(g->m, a.reps);
+    int2* longs = nullptr;
+    unsigned long long* sum = nullptr;
+    const unsigned long long sw = ((unsigned long long)a.n + 63) / 64;  // summary words
+    if ((size_t)(a.K + 4) * a.cap >= lcap + sw) {
+      longs = a.win;
+      hipLaunchKernelGGL(k_fill, dim3(1), dim3(kWave), 0, stream, (int*)&a.ctl->pred_slices.v, 2ll, 0);
+      // The parity filter pays where a vertex's neighbours are scattered and
+      // their dist reads miss the cache, which mean degree >= kPredParDeg
+      // stands for (power-law graphs; a road grid's neighbours are local and
+      // the extra read only adds latency there).
+      if (g->m >= (long long)kPredParDeg * a.nbase) {
+        sum = reinterpret_cast<unsigned long long*>(a.win + lcap);
+        hipLaunchKernelGGL(k_pred_summary, dim3(fill_grid), dim3(kBlock), 0, stream, a, sum);
+      }
+    }
+    if (sum) {
+      hipLaunchKernelGGL((k_pred_edges<W, true>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+                         (const unsigned long long*)sum);
+      hipLaunchKernelGGL((k_pred_long<W, true>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+                         (const unsigned long long*)sum);
+    } else {
+      hipLaunchKernelGGL((k_pred_edges<W, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+                         (const unsigned long long*)nullptr);
+      if (longs)
+        hipLaunchKernelGGL((k_pred_long<W, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+                           (const unsigned long long*)nullptr);
+    }
     hipLaunchKernelGGL(k_pred_fix, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n);
     hipLaunchKernelGGL(k_pred_sources, dim3(src_grid), dim3(kBlock), 0, stream, a, pred);
     if (pred_edge) hipLaunchKernelGGL(k_pred_edge_ids, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, pred_edge);
   } else if (stats) {
-    hipLaunchKernelGGL(k_pred_edges<W>, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr);
+    hipLaunchKernelGGL((k_pred_edges<W, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr,
+                       (int2*)nullptr, 0ull, (const unsigned long long*)nullptr);
   }
   if (timing) (void)hipEventRecord(t_timers.ev[3], stream);
   if (hipGetLastError() != hipSuccess) return fail(OG_ERR_HIP);
