@@ -3132,8 +3132,17 @@ og_status og_sssp_backward_f32(const og_graph_f32* g, const int32_t* pred, const
   hipLaunchKernelGGL(og::k_bw_init, dim3(grid), dim3(og::kBlock), 0, st, grad_dist, g->n, grad_w, (long long)g->m,
                      acc, kids, pending);
   hipLaunchKernelGGL(og::k_bw_count, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, kids, pending);
-  hipLaunchKernelGGL(og::k_bw_climb, dim3(grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, grad_w, acc, kids,
-                     pending);
+  // A wavefront runs until its longest climb ends, so a thread that takes
+  // several leaves in turn adds their climbs up: on a deep tree (a road
+  // grid's, thousands of levels) every vertex gets a thread of its own.  On
+  // a power-law graph (mean degree >= kPredParDeg) the tree is shallow and
+  // the hubs' many children contend for the hubs' sums, which the smaller
+  // grid-stride launch spreads out.
+  const int climb_grid = g->m >= (long long)og::kPredParDeg * g->n
+                             ? grid
+                             : (int)(((long long)g->n + og::kBlock - 1) / og::kBlock);
+  hipLaunchKernelGGL(og::k_bw_climb, dim3(climb_grid), dim3(og::kBlock), 0, st, pred, pred_edge, g->n, grad_w, acc,
+                     kids, pending);
   if (hipGetLastError() != hipSuccess) return OG_ERR_HIP;
   return OG_OK;
 }
