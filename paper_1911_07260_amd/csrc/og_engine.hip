@@ -109,6 +109,9 @@ __host__ __device__ inline unsigned long long slice_cap(long long m) {
 constexpr int kPredLong = 1024;
 constexpr int kPredSlice = 2048;
 constexpr int kPredIlp = 4;  // groups of 64 edges whose loads a wavefront keeps in flight
+// Edges per lane whose loads and atomics the engine keeps in flight in a
+// batch of more than one workgroup's worth of edges.
+constexpr int kEdgeIlp = 2;
 constexpr int kPredParDeg = 8;  // mean degree from which the parity filter is used
 __host__ __device__ inline unsigned long long pred_slice_cap(long long m, int reps) {
   return (unsigned long long)reps * (unsigned long long)(m / kPredSlice + m / kPredLong + 1);
@@ -297,6 +300,10 @@ __device__ __forceinline__ void set_status(Ctl* c, int st) {
 struct IntW {
   static constexpr int kInfBits = INT_MAX;
   static constexpr bool kSplit = false;
+  // process_batch takes batches of more than kBlock edges kEdgeIlp edges
+  // per lane at a time (relax_wide); the plain int32 engine does without,
+  // as the extra registers cost it a wavefront per SIMD on the road graphs
+  static constexpr bool kWide = false;
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
   static constexpr bool kBin = false;
@@ -330,6 +337,7 @@ struct IntW {
 struct FloatW {
   static constexpr int kInfBits = 0x7f800000;  // +inf
   static constexpr bool kSplit = false;
+  static constexpr bool kWide = true;
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
   static constexpr bool kBin = false;
@@ -377,6 +385,7 @@ struct CoreW : IntW {
 // instantiation, so the other engines' code is not touched by it.
 struct SplitW : IntW {
   static constexpr bool kSplit = true;
+  static constexpr bool kWide = true;
   __device__ static bool light(const Args& a, int wraw) { return wraw < (int)a.delta; }
 };
 
@@ -552,6 +561,94 @@ __device__ void route_push(const Args& a, Smem& s, Counters& c, bool has, int v,
   wave_push_global(a, s, c, has, tgt, v, d, b);
 }
 
+// The edge loop of process_batch for a batch of more than kBlock edges
+// (throughput-bound: every edge is filtered by a plain load of dist[u]).
+// Each lane takes kEdgeIlp edges per step and keeps their loads, filter
+// reads and atomics in flight together; the improved vertices are then
+// filed as by process_batch.  The batch arrays (boff, bstart, bd, bv, bvo)
+// are in place.
+template <class W>
+__device__ void relax_wide(const Args& a, Smem& s, Counters& c, bool from_lds, int total, int nb, unsigned cur) {
+  const int tid = threadIdx.x;
+  for (int base = 0; base < total; base += kBlock * kEdgeIlp) {
+    int u[kEdgeIlp], ub[kEdgeIlp], wt[kEdgeIlp], ds[kEdgeIlp], dn[kEdgeIlp], cu[kEdgeIlp], old[kEdgeIlp];
+    unsigned nd[kEdgeIlp], b[kEdgeIlp];
+    bool go[kEdgeIlp];
+#pragma unroll
+    for (int j = 0; j < kEdgeIlp; ++j) {  // edge loads
+      const int e = base + j * kBlock + tid;
+      go[j] = e < total;
+      u[j] = ub[j] = wt[j] = ds[j] = dn[j] = 0;
+      if (go[j]) {
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s.boff[mid] <= e) lo = mid;
+          else hi = mid - 1;
+        }
+        const int edge = s.bstart[lo] + (e - s.boff[lo]);
+        ds[j] = s.bd[lo];
+        ub[j] = W::kSplit ? a.ecol[edge] : a.col[edge];
+        wt[j] = W::kSplit ? a.ew[edge] : a.w[edge];
+        dn[j] = from_lds ? a.dist[s.bv[lo]] : ds[j];
+        u[j] = ub[j] + s.bvo[lo];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kEdgeIlp; ++j) {  // new distances, then the filter reads
+      nd[j] = b[j] = 0;
+      cu[j] = 0;
+      if (go[j]) {
+        c.relax++;
+        int ndi = 0;
+        go[j] = ds[j] <= dn[j] && W::add(a, ds[j], wt[j], &ndi);
+        if (go[j]) {
+          nd[j] = (unsigned)ndi;
+          const unsigned key = W::key(a, u[j], ndi);
+          go[j] = !(a.tgts && key >= (unsigned)s.tb[query_of(a, u[j])]);  // cannot improve the target
+          b[j] = W::bucket(a, key);
+          if (b[j] < cur) b[j] = cur;  // only an inconsistent A* estimate gets here
+          if (go[j]) cu[j] = a.dist[u[j]];
+        }
+      }
+    }
+    long long q0[kEdgeIlp], q1[kEdgeIlp];
+    int ql[kEdgeIlp];
+#pragma unroll
+    for (int j = 0; j < kEdgeIlp; ++j) {  // the atomics (with the chased rows)
+      q0[j] = q1[j] = 0;
+      ql[j] = 0;
+      old[j] = 0;
+      go[j] = go[j] && (int)nd[j] < cu[j];
+      if (go[j]) {
+        if (a.fused && b[j] == cur) {
+          q0[j] = a.row_ptr[ub[j]];
+          q1[j] = a.row_ptr[ub[j] + 1];
+          if constexpr (W::kSplit) ql[j] = a.lsplit[ub[j]];
+        }
+        old[j] = atomicMin(&a.dist[u[j]], (int)nd[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kEdgeIlp; ++j) {  // file the improved vertices
+      const bool has = go[j] && (int)nd[j] < old[j];
+      int r0 = 0, rdeg = 0;
+      if (has) {
+        c.improve++;
+        r0 = (int)q0[j];
+        rdeg = (int)(q1[j] - q0[j]);
+        if constexpr (W::kSplit) rdeg = ql[j] | (rdeg > ql[j] ? kHeavyBit : 0);
+      }
+      if (a.lazy) {
+        const bool first = has && atomicExch(&a.aux[u[j]], 1) == 0;
+        wave_append_buf(a, first, u[j]);
+      } else {
+        route_push(a, s, c, has, u[j], (int)nd[j], b[j], r0, rdeg);
+      }
+    }
+  }
+}
+
 // Relaxes the out-edges of one batch of up to kBlock entries; lane i holds
 // entry i (v < 0: none).  Edges of the batch are spread evenly over the
 // workgroup (flat expansion with a binary search over degree offsets), so a
@@ -655,6 +752,12 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
   // one pass over its edges) goes straight to the atomic; larger batches
   // (throughput-bound) filter.
   const bool prefilter = !from_lds || total > kBlock;
+  if constexpr (W::kWide) {
+    if (total > kBlock) {
+      relax_wide<W>(a, s, c, from_lds, total, nb, cur);
+      return;
+    }
+  }
   for (int base = 0; base < total; base += kBlock) {
     const int e = base + tid;
     bool has = false;
