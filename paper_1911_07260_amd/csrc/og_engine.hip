@@ -2185,17 +2185,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(int* p, long long n, int value)
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) p[v] = value;
 }
 
-// Canonical predecessors: for every edge (u,v) of every query copy with
-// dist[u] finite and dist[u] + w == dist[v], pred[v] = min(pred[v], u) (base
-// vertex ids).  One wavefront per chunk of 64 consecutive source vertices of
-// one copy: a wavefront scan numbers the chunk's edges, which the lanes then
-// take 64 at a time, each finding its source lane by a binary search over
-// the lanes' offsets; the edge loads of consecutive lanes are contiguous
-// within a row.  When longs is given, a row longer than kPredLong edges is
-// left out and listed instead as slices of kPredSlice edges (at most lcap
-// entries) for k_pred_long.  With the parity summary sum, edges that cannot
-// be tight by parity skip their dist read.  Also counts reached vertices and
-// edges.  pred == nullptr: counts only.
 // Parity summary of the final distances for the predecessor pass: bit
 // v % 64 of word v / 64 is the lowest bit of dist[v]'s bit pattern (one bit
 // per vertex, 32 times smaller than dist).
@@ -2208,12 +2197,25 @@ __global__ __launch_bounds__(kBlock) void k_pred_summary(Args a, unsigned long l
     if (lane_id() == 0 && v < nv) sum[v >> 6] = word;
   }
 }
+
 // Whether the summary allows dist[u] to equal the would-be distance c: an
 // edge whose c has the other parity is not tight, and its random dist read
 // is saved.
 __device__ __forceinline__ bool par_ok(const unsigned long long* sum, long long u, unsigned c) {
   return ((unsigned)(sum[u >> 6] >> (u & 63)) & 1u) == (c & 1u);
 }
+
+// Canonical predecessors: for every edge (u,v) of every query copy with
+// dist[u] finite and dist[u] + w == dist[v], pred[v] = min(pred[v], u) (base
+// vertex ids).  One wavefront per chunk of 64 consecutive source vertices of
+// one copy: a wavefront scan numbers the chunk's edges, which the lanes then
+// take 64 at a time, each finding its source lane by a binary search over
+// the lanes' offsets; the edge loads of consecutive lanes are contiguous
+// within a row.  When longs is given, a row longer than kPredLong edges is
+// left out and listed instead as slices of kPredSlice edges (at most lcap
+// entries) for k_pred_long.  With the parity summary (kPar), edges that
+// cannot be tight by parity skip their dist read.  Also counts reached vertices and
+// edges.  pred == nullptr: counts only.
 template <class W, bool kPar>
 __global__ __launch_bounds__(kBlock) void k_pred_edges(Args a, int* pred, int2* longs, unsigned long long lcap,
                                                        const unsigned long long* sum) {
