@@ -44,6 +44,44 @@ def test_sssp_batch_grid(orc, update, delta):
     assert st["reached_vertices"] == 8 * g.n
 
 
+@pytest.mark.parametrize("update", [og.OG_EAGER_WITH_FUSION, og.OG_EAGER_NO_FUSION])
+def test_sssp_batch_and_multi_power_law(orc, update):
+    """A power-law graph in one launch: R-MAT 14 has rows longer than the
+    predecessor pass's per-chunk limit (up to 3,627 edges, listed as slices)
+    and a mean degree that turns on its parity filter, in every query copy;
+    distances and canonical predecessors of every query, and the
+    multi-source distances, equal the oracle's."""
+    g = gg.rmat(14, 16, seed=0)
+    dg = og.DeviceGraph.from_host(g, DEV)
+    srcs = [int(x) for x in gg.pick_sources(g, 6, seed=12)]
+    say(f"sssp_batch rmat14 nq=6 update={update}")
+    d, p, st = og.sssp_batch(dg, srcs, og.Schedule(delta=32, update=update))
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    d, p = d.cpu().numpy(), p.cpu().numpy()
+    for q, s in enumerate(srcs):
+        rd, rp = orc.sssp(g, s)
+        assert np.array_equal(d[q], rd), q
+        assert np.array_equal(p[q], rp), q
+    say(f"sssp_multi rmat14 nsrc=6 update={update}")
+    dm, pm, st = og.sssp_multi(dg, srcs, og.Schedule(delta=32, update=update))
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    ref = np.min(np.stack([orc.sssp(g, s)[0] for s in srcs]), axis=0)
+    dm, pm = dm.cpu().numpy(), pm.cpu().numpy()
+    assert np.array_equal(dm, ref)
+    # canonical predecessors under the multi-source distances, by brute force
+    # over every edge: the smallest tight in-neighbour, each source its own
+    src_of = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    du = ref.astype(np.int64)
+    tight = (du[src_of] < INF) & (du[src_of] + g.w == du[g.col])
+    want = np.full(g.n, np.iinfo(np.int64).max)
+    np.minimum.at(want, g.col[tight], src_of[tight])
+    want[ref == INF] = -1
+    want[srcs] = srcs
+    assert np.array_equal(pm.astype(np.int64), want)
+
+
 @pytest.mark.parametrize("nq", [1, 5, 32])
 def test_sssp_batch_road(orc, road128, nq):
     g, dg = road128
