@@ -153,6 +153,33 @@ def test_small_queues_fall_back_to_far(orc, road256):
         assert st["status"] == og.OG_ERR_WORKSPACE
 
 
+def test_pred_pass_with_and_without_queue_room(orc):
+    """The predecessor pass keeps its long-row slice list and parity summary
+    where the queues were; with queues too small for them every row stays in
+    its chunk and every dist read is made.  A weighted path with four hubs
+    joined to every path vertex (rows of 2,000 edges, mean degree 10) gives
+    the same canonical predecessors both ways."""
+    L, H = 2000, 4
+    src, dst, w = [], [], []
+    for i in range(L - 1):
+        src += [i, i + 1]
+        dst += [i + 1, i]
+        w += [1 + i % 3] * 2
+    for h in range(L, L + H):
+        for i in range(L):
+            src += [h, i]
+            dst += [i, h]
+            w += [1_000_000 + i % 7] * 2
+    g = gg.from_edges(L + H, src, dst, w)
+    assert g.m >= 8 * g.n and np.diff(g.row_ptr).max() > 1024
+    dg = og.DeviceGraph.from_host(g, DEV)
+    for cap in (0, 8):  # 0: the default capacity
+        say(f"pred pass, path with hubs, queue_capacity={cap}")
+        d, p, st = run_sssp(dg, 0, og.Schedule(delta=64, window_buckets=2, queue_capacity=cap))
+        assert st["status"] == 0, st["status"]
+        assert_exact(orc, g, 0, d, p, f"hubs cap={cap}")
+
+
 def test_queue_overflow_is_reported(road256):
     g, dg = road256
     say("queue_capacity 1024 on road256 delta=2^20 unfused -> workspace error")
