@@ -116,6 +116,15 @@ constexpr int kPredParDeg = 8;  // mean degree from which the parity filter is u
 __host__ __device__ inline unsigned long long pred_slice_cap(long long m, int reps) {
   return (unsigned long long)reps * (unsigned long long)(m / kPredSlice + m / kPredLong + 1);
 }
+// Light/heavy split: a settled vertex whose heavy part has more than
+// kHeavySlice edges is filed for the heavy round as one entry per slice of
+// kHeavySlice edges, (v, slice), so that the slices of a hub are spread over
+// workgroups; any other vertex as (v, -1), its whole heavy part.  A heavy
+// list then holds at most n + m / kHeavySlice entries per copy.
+constexpr int kHeavySlice = 4096;
+__host__ __device__ inline long long heavy_cap(long long nv, long long m, int reps) {
+  return nv + (long long)reps * (m / kHeavySlice) + 1;
+}
 // Light/heavy split: LDS ring entries carry a vertex's light-edge count with
 // this bit set when the vertex also has heavy edges.
 constexpr int kHeavyBit = 1 << 30;
@@ -214,7 +223,7 @@ struct Args {
   const int* ew;      // [m] their weights
   const int* lsplit;  // [nbase] light edges per row
   unsigned* hmark;    // [n] 1 + the generation of the last heavy list holding the vertex
-  int2* heavy;        // 2 lists of hcap (v, 0) entries: vertices settled in a bucket
+  int2* heavy;        // 2 lists of hcap (v, slice) entries: vertices settled in a bucket
   unsigned hcap;
   long long m;
   int bin_thread;    // degree bins (BinW): lane bin up to this degree (<= kBinLane)
@@ -516,19 +525,29 @@ __device__ void wave_append_buf(const Args& a, bool has, int v) {
 // list (the generation stamp in hmark).  The stamp is per list, not per
 // bucket: with an A* estimate a heavy edge can lead back into the current
 // bucket, so a vertex whose heavy edges were relaxed in the bucket's heavy
-// round can improve again and must be filed again.  One atomic per wavefront.
-__device__ void wave_append_heavy(const Args& a, const Smem& s, bool has, int v) {
+// round can improve again and must be filed again.  nheavy: the heavy
+// part's length when known (more than kHeavySlice: one entry per slice),
+// else -1.  One atomic per wavefront.
+__device__ void wave_append_heavy(const Args& a, const Smem& s, bool has, int v, int nheavy) {
   const unsigned stamp = s.hgen + 1u;
   if (has) has = atomicMax(&a.hmark[v], stamp) < stamp;
-  const unsigned long long m = __ballot(has);
-  if (m == 0) return;
-  const int leader = __ffsll((long long)m) - 1;
+  if (__ballot(has) == 0) return;
+  const int nsl = !has ? 0 : (nheavy > kHeavySlice ? (nheavy + kHeavySlice - 1) / kHeavySlice : 1);
+  const int lane = (int)lane_id();
+  int inc = nsl;  // inclusive scan of the entry counts over the wavefront
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  const int total = __shfl(inc, kWave - 1);
   unsigned base = 0;
-  if ((int)lane_id() == leader) base = atomicAdd(&a.ctl->heavy_tail[s.hout].v, (unsigned)__popcll(m));
-  base = __shfl(base, leader);
-  if (has) {
-    const unsigned pos = base + (unsigned)__popcll(m & lanemask_lt());
-    if (pos < a.hcap) st_entry(a.heavy + (size_t)s.hout * a.hcap, pos, v, 0);
+  if (lane == 0) base = atomicAdd(&a.ctl->heavy_tail[s.hout].v, (unsigned)total);
+  base = __shfl(base, 0);
+  const unsigned first = base + (unsigned)(inc - nsl);
+  for (int k = 0; k < nsl; ++k) {
+    const unsigned pos = first + (unsigned)k;
+    if (pos < a.hcap) st_entry(a.heavy + (size_t)s.hout * a.hcap, pos, v, nsl > 1 ? k : -1);
     else set_status(a.ctl, OG_ERR_WORKSPACE);
   }
 }
@@ -674,7 +693,7 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
   const int d = W::kSplit && v >= 0 && !from_lds && s.in_kind == kInHeavy
                     ? (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + v)
                     : ent.y;
-  int deg = 0, start = 0, voff = 0;
+  int deg = 0, start = 0, voff = 0, nheavy = -1;
   bool repush = false, settle = false;
   unsigned rb = 0;
   if (v >= 0) {
@@ -689,12 +708,18 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
         deg = ent.w;
       }
     } else if (W::kSplit && s.in_kind == kInHeavy) {
-      // the bucket is finished: the heavy part of the vertex's row
+      // the bucket is finished: the heavy part of the vertex's row, or its
+      // slice ent.y
       const long long r0 = a.row_ptr[vb];
       const long long r1 = a.row_ptr[vb + 1];
       const int l = a.lsplit[vb];
       start = (int)r0 + l;
       deg = (int)(r1 - r0) - l;
+      if (ent.y >= 0) {
+        const long long skip = (long long)ent.y * kHeavySlice;
+        start += (int)(skip < deg ? skip : deg);
+        deg = skip < deg ? (deg - (int)skip < kHeavySlice ? deg - (int)skip : kHeavySlice) : -1;
+      }
     } else {
       // issued together: the staleness check does not delay the row lookup
       const int cv = a.dist[v];
@@ -717,6 +742,7 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
         if constexpr (W::kSplit) {
           deg = l;
           settle = (int)(r1 - r0) > l;
+          nheavy = (int)(r1 - r0) - l;
         } else {
           deg = (int)(r1 - r0);
         }
@@ -736,7 +762,7 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
     if (repush) tgt = rb < s.win_hi ? (int)(rb & (unsigned)(a.K - 1)) : a.K + 1;
     wave_push_global(a, s, c, repush, tgt, v, d, rb);
   }
-  if constexpr (W::kSplit) wave_append_heavy(a, s, settle, v);  // heavy edges wait for the bucket's end
+  if constexpr (W::kSplit) wave_append_heavy(a, s, settle, v, nheavy);  // heavy edges wait for the bucket's end
   int total;
   const int off = block_excl_scan(deg, s, &total);
   s.boff[tid] = off;
@@ -2612,8 +2638,9 @@ size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   if (r->update == OG_LAZY_UPDATE) b += 2 * vec_bytes(nv);
   if (sh.core) b += vec_bytes(nv);
   // light/heavy split: col and w copies, light counts, long-row list, bucket
-  // stamps and two heavy lists of (v, 0) entries
-  if (split_on(r, sh)) b += 2 * vec_bytes(g->m) + 2 * vec_bytes(g->n) + vec_bytes(nv) + 4 * vec_bytes(nv);
+  // stamps and two heavy lists of (v, slice) entries
+  if (split_on(r, sh))
+    b += 2 * vec_bytes(g->m) + 2 * vec_bytes(g->n) + vec_bytes(nv) + 4 * vec_bytes(heavy_cap(nv, g->m, sh.reps));
   // pull direction: frontier marks ((stamp, distance) pairs; k-core: a
   // bitmap) and the long rows' slices
   if (pull_mode(r) != kPullNever)
@@ -2843,7 +2870,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       a.hmark = (unsigned*)(base + off);
       off += vec_bytes(a.n);
       a.heavy = (int2*)(base + off);
-      a.hcap = (unsigned)a.n;
+      a.hcap = (unsigned)heavy_cap(a.n, g->m, a.reps);
       a.ecol = split_col;
       a.ew = split_w;
       a.lsplit = split_l;
