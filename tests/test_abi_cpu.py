@@ -83,11 +83,14 @@ def test_workspace_bytes():
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s2)) == base + vec
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s3)) == base + 3 * vec
     # light/heavy split: + split copy of col and w, light counts, long-row
-    # list, bucket stamps and two heavy lists of (v, 0) entries
+    # list, bucket stamps and two heavy lists of (v, slice) entries, each
+    # n + m / 4096 + 1 long (a heavy part is filed once per 4,096 edges)
     s4 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, flags=og.OG_FLAG_LIGHT_HEAVY).to_c()
-    evec = (g.m * 4 + 255) // 256 * 256
-    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s4)) == (65536 + 256 + 12 * 5000 * 8 + 2 * evec
-                                                                         + 3 * vec + 4 * vec)
+    for gs in (g, _fake_graph(1000, 100_000)):
+        evec = (gs.m * 4 + 255) // 256 * 256
+        hvec = ((gs.n + gs.m // 4096 + 1) * 4 + 255) // 256 * 256
+        assert lib.og_workspace_bytes(ctypes.byref(gs), ctypes.byref(s4)) == (65536 + 256 + 12 * 5000 * 8
+                                                                              + 2 * evec + 3 * vec + 4 * hvec)
     # pull direction (lazy only): + frontier marks (SSSP: 8 bytes per vertex; k-core: one bit) and the
     # long rows' slice list
     for fl in (og.OG_FLAG_DENSE_PULL, og.OG_FLAG_HYBRID_DIRECTION):
