@@ -53,6 +53,38 @@ def test_split_parity(orc, graphs, kind, delta, update, engine):
         check(orc, g, int(src), d, p, tag)
 
 
+@pytest.mark.parametrize("update", [og.OG_EAGER_WITH_FUSION, og.OG_EAGER_NO_FUSION])
+def test_split_hub_heavy_slices(orc, update):
+    """Heavy parts longer than 4,096 edges are filed as one heavy-list entry
+    per 4,096-edge slice: a path of light edges with two hubs joined to every
+    path vertex by heavy edges (heavy parts of 9,000 edges, three slices each,
+    many of them shortening paths) gives the oracle's distances and canonical
+    predecessors."""
+    N, delta = 9000, 64
+    rng = np.random.default_rng(41)
+    src, dst, w = [], [], []
+    pw = rng.integers(1, 8, N - 1)
+    for i in range(N - 1):
+        src += [i, i + 1]
+        dst += [i + 1, i]
+        w += [int(pw[i])] * 2
+    for h in (N, N + 1):
+        hw = rng.integers(delta, 3 * delta, N)
+        for i in range(N):
+            src += [h, i]
+            dst += [i, h]
+            w += [int(hw[i])] * 2
+    g = gg.from_edges(N + 2, src, dst, w)
+    dg = og.DeviceGraph.from_host(g, DEV)
+    for s0 in (0, N // 2, N + 1):
+        tag = f"split hubs src={s0} update={update}"
+        say(tag)
+        d, p, st = og.sssp(dg, s0, og.Schedule(delta=delta, update=update, flags=LH))
+        torch.cuda.synchronize()
+        assert st["status"] == 0
+        check(orc, g, s0, d, p, tag)
+
+
 def test_split_reduces_relaxations(orc, graphs):
     g, dg = graphs["rmat"]
     src = int(gg.pick_sources(g, 1, seed=32)[0])
