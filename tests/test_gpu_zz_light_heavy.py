@@ -83,6 +83,13 @@ def test_split_hub_heavy_slices(orc, update):
         torch.cuda.synchronize()
         assert st["status"] == 0
         check(orc, g, s0, d, p, tag)
+    # the same three queries in one launch: every copy files its hubs' slices
+    say(f"split hubs batch x3 update={update}")
+    d, p, st = og.sssp_batch(dg, [0, N // 2, N + 1], og.Schedule(delta=delta, update=update, flags=LH))
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    for q, s0 in enumerate((0, N // 2, N + 1)):
+        check(orc, g, s0, d[q], p[q], f"split hubs batch q={q}")
 
 
 def test_split_reduces_relaxations(orc, graphs):
