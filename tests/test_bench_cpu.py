@@ -36,6 +36,22 @@ def test_committed_profile_is_current():
     assert bench.read_traffic(512) is not None
 
 
+def test_kernel_profiles_are_current():
+    """The committed kernel traces and counter summaries that stand for the
+    current engine were taken on it (a code change without retaking them
+    fails here); the two older counter sets say which code they were taken on."""
+    current = ["k_persistent_road4096_traffic.txt", "kernels_road4096_d512_fused.txt",
+               "kernels_kcore_rmat24_lazy.txt", "kernels_sssp_rmat24_d32_unfused.txt",
+               "kernels_sssp_rmat24_split_d64_kept_counters.txt"]
+    h = bench.engine_hash()
+    pdir = os.path.join(os.path.dirname(bench.TRAFFIC_FILE))
+    for name in current:
+        text = open(os.path.join(pdir, name)).read()
+        assert "engine_code_sha256_16: " + h in text, name
+    for name in ("k_persistent_road4096_stalls.txt", "k_persistent_road4096_bins_counters.txt"):
+        assert "engine_code_sha256_16: " in open(os.path.join(pdir, name)).read(), name
+
+
 def test_summarize_rocpd(tmp_path, capsys):
     db = tmp_path / "r.db"
     con = sqlite3.connect(db)
