@@ -41,6 +41,13 @@ from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_GRAPH_ROU
 
 INF = 2**31 - 1
 
+
+def _require(ok: bool, what: str) -> None:
+    """Argument check that survives python -O (a failed check never reaches
+    the library with a buffer of the wrong type or size)."""
+    if not ok:
+        raise ValueError(what)
+
 __all__ = [
     "DeviceGraph", "Schedule", "Workspace", "sssp", "wbfs", "ppsp", "astar", "sssp_batch", "ppsp_batch",
     "astar_batch", "sssp_multi", "kcore", "workspace_bytes", "status_string", "version", "INF", "OgError",
@@ -74,9 +81,13 @@ class DeviceGraph:
     """Directed CSR graph resident on a device (int64 row_ptr, int32 col, w)."""
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, w: torch.Tensor | None):
-        assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32
-        assert row_ptr.is_contiguous() and col.is_contiguous()
-        assert w is None or (w.dtype == torch.int32 and w.is_contiguous())
+        _require(row_ptr.dtype == torch.int64 and col.dtype == torch.int32,
+                 "DeviceGraph: row_ptr must be int64 and col int32")
+        _require(row_ptr.is_contiguous() and col.is_contiguous(), "DeviceGraph: row_ptr and col must be contiguous")
+        _require(w is None or (w.dtype == torch.int32 and w.is_contiguous()),
+                 "DeviceGraph: w must be a contiguous int32 tensor")
+        _require(row_ptr.numel() >= 2, "DeviceGraph: row_ptr needs n + 1 >= 2 entries")
+        _require(w is None or w.numel() == col.numel(), "DeviceGraph: w and col must have the same length")
         self.row_ptr, self.col, self.w = row_ptr, col, w
         self.n = row_ptr.numel() - 1
         self.m = col.numel()
@@ -158,7 +169,10 @@ def _call(fn_name, graph, args_mid, schedule, want_pred, ws, stream, out_dist=No
     dist = out_dist if out_dist is not None else torch.empty(shape, dtype=torch.int32, device=dev)
     pred = out_pred if out_pred is not None else (
         torch.empty(shape, dtype=torch.int32, device=dev) if want_pred else None)
-    assert dist.numel() == n and dist.dtype == torch.int32 and dist.is_contiguous()
+    _require(dist.numel() == n and dist.dtype == torch.int32 and dist.is_contiguous(),
+             f"output dist must be a contiguous int32 tensor of {n} entries")
+    _require(pred is None or (pred.numel() == n and pred.dtype == torch.int32 and pred.is_contiguous()),
+             f"output pred must be a contiguous int32 tensor of {n} entries")
     buf, nbytes = _workspace(graph, schedule, ws, batch=batch, multi=multi)
     g = graph.to_c()
     s = schedule.to_c()
@@ -199,7 +213,8 @@ def ppsp(graph: DeviceGraph, src: int, dst: int, schedule: Schedule | None = Non
 def astar(graph: DeviceGraph, src: int, dst: int, h: torch.Tensor, schedule: Schedule | None = None,
           pred: bool = True, ws: Workspace | None = None, stream=None, **kw):
     """A* (og_astar) with per-vertex estimate h (int32 device tensor)."""
-    assert h.dtype == torch.int32 and h.is_contiguous() and h.numel() == graph.n
+    _require(h.dtype == torch.int32 and h.is_contiguous() and h.numel() == graph.n,
+             f"h must be a contiguous int32 tensor of {graph.n} entries")
     return _call("og_astar", graph, [int(src), int(dst), ctypes.c_void_p(h.data_ptr())], schedule, pred,
                  ws, stream, **kw)
 
@@ -222,7 +237,7 @@ def ppsp_batch(graph: DeviceGraph, srcs, dsts, schedule: Schedule | None = None,
                ws: Workspace | None = None, stream=None, **kw):
     """nq point-to-point queries in one launch (og_ppsp_batch)."""
     s_, t_ = _host_ids(srcs), _host_ids(dsts)
-    assert len(s_) == len(t_)
+    _require(len(s_) == len(t_), "ppsp_batch: srcs and dsts must have the same length")
     return _call("og_ppsp_batch", graph, [ctypes.c_void_p(s_.ctypes.data), ctypes.c_void_p(t_.ctypes.data), len(s_)],
                  schedule, pred, ws, stream, nq=len(s_), batch=len(s_), **kw)
 
@@ -231,8 +246,9 @@ def astar_batch(graph: DeviceGraph, srcs, dsts, h: torch.Tensor, schedule: Sched
                 pred: bool = True, ws: Workspace | None = None, stream=None, **kw):
     """nq A* queries in one launch (og_astar_batch); h is [nq, n] int32."""
     s_, t_ = _host_ids(srcs), _host_ids(dsts)
-    assert len(s_) == len(t_)
-    assert h.dtype == torch.int32 and h.is_contiguous() and h.numel() == graph.n * len(s_)
+    _require(len(s_) == len(t_), "astar_batch: srcs and dsts must have the same length")
+    _require(h.dtype == torch.int32 and h.is_contiguous() and h.numel() == graph.n * len(s_),
+             f"h must be a contiguous int32 tensor of {graph.n * len(s_)} entries")
     return _call("og_astar_batch", graph, [ctypes.c_void_p(s_.ctypes.data), ctypes.c_void_p(t_.ctypes.data), len(s_),
                                            ctypes.c_void_p(h.data_ptr())],
                  schedule, pred, ws, stream, nq=len(s_), batch=len(s_), **kw)
@@ -263,7 +279,8 @@ def kcore(graph: DeviceGraph, schedule: Schedule | None = None, ws: Workspace | 
         ws = _default_ws.setdefault(str(graph.device), Workspace(graph.device))
     buf = ws.get(nbytes)
     core = out if out is not None else torch.empty(graph.n, dtype=torch.int32, device=graph.device)
-    assert core.numel() == graph.n and core.dtype == torch.int32 and core.is_contiguous()
+    _require(core.numel() == graph.n and core.dtype == torch.int32 and core.is_contiguous(),
+             f"output core must be a contiguous int32 tensor of {graph.n} entries")
     st = OgStats()
     if stream is None:
         stream = torch.cuda.current_stream(graph.device)

@@ -31,9 +31,15 @@ from dataclasses import asdict, dataclass, field
 import numpy as np
 import torch
 
-from . import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_DEGREE_BINS, OG_FLAG_DENSE_PULL,
-               OG_FLAG_HYBRID_DIRECTION, OG_FLAG_TIMING, OG_LAZY_UPDATE, DeviceGraph, Schedule, Workspace, astar_batch,
-               ppsp_batch, sssp, sssp_batch)
+from . import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE, OG_FLAG_DEGREE_BINS,
+               OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_TIMING, OG_LAZY_UPDATE, DeviceGraph, OgError,
+               Schedule, Workspace, astar_batch, ppsp_batch, sssp, sssp_batch)
+
+# Statuses that make a candidate a bad schedule rather than a failure: its
+# queues overflowed the workspace, or it needed more rounds than the base
+# schedule allows.  Every other error (an invalid argument, a HIP failure,
+# an internal consistency check) is raised to the caller.
+_CANDIDATE_ERRORS = (OG_ERR_WORKSPACE, OG_ERR_ROUND_LIMIT)
 
 _DIRECTIONS = OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION
 _CHOSEN = _DIRECTIONS | OG_FLAG_DEGREE_BINS  # flags the search may set
@@ -125,7 +131,9 @@ class Autotuner:
         for _ in range(self.repeats):
             try:
                 ms.append(self.runner(s))
-            except Exception:  # a schedule that overflows its queues is just a bad candidate
+            except OgError as e:
+                if e.status not in _CANDIDATE_ERRORS:
+                    raise
                 ok = False
                 break
         val = float(np.median(ms)) if ok else math.inf

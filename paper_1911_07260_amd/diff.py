@@ -22,7 +22,8 @@ __all__ = ["sssp_f32", "sssp_backward_f32", "ShortestPathDistances", "shortest_p
 
 
 def _graph_f32(graph, w: torch.Tensor) -> OgGraphF32:
-    assert w.dtype == torch.float32 and w.is_contiguous() and w.numel() == graph.m
+    if not (w.dtype == torch.float32 and w.is_contiguous() and w.numel() == graph.m):
+        raise ValueError(f"w must be a contiguous float32 tensor of the graph's {graph.m} edges")
     return OgGraphF32(graph.n, graph.m, graph.row_ptr.data_ptr(), graph.col.data_ptr() if graph.m else None,
                       w.data_ptr() if graph.m else None)
 

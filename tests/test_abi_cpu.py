@@ -194,3 +194,26 @@ def test_workspace_too_small():
     rc = lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), ctypes.c_void_p(0x4000), None,
                      ctypes.c_void_p(0x10000), ctypes.c_size_t(need - 256), ctypes.byref(st), None)
     assert rc == og.OG_ERR_WORKSPACE
+
+
+def test_binding_argument_checks_survive_optimisation():
+    """Wrong tensor types are rejected by a raised ValueError, not an
+    assert that python -O would strip (CPU tensors: nothing is launched)."""
+    import torch
+    rp = torch.tensor([0, 1, 2], dtype=torch.int64)
+    col = torch.tensor([1, 0], dtype=torch.int32)
+    w = torch.tensor([3, 3], dtype=torch.int32)
+    og.DeviceGraph(rp, col, w)  # well formed
+    with pytest.raises(ValueError):
+        og.DeviceGraph(rp.to(torch.int32), col, w)
+    with pytest.raises(ValueError):
+        og.DeviceGraph(rp, col.to(torch.int64), w)
+    with pytest.raises(ValueError):
+        og.DeviceGraph(rp, col, w.to(torch.float32))
+    with pytest.raises(ValueError):
+        og.DeviceGraph(rp, col, w[:1])
+    with pytest.raises(ValueError):
+        og.DeviceGraph(torch.zeros(1, dtype=torch.int64), col[:0], w[:0])
+    src = open(os.path.join(ROOT, "paper_1911_07260_amd", "__init__.py")).read()
+    src += open(os.path.join(ROOT, "paper_1911_07260_amd", "diff.py")).read()
+    assert not re.search(r"^\s*assert\b", src, flags=re.M)

@@ -2,8 +2,11 @@
 GPU: the runner is a plain function of the schedule)."""
 import math
 
-from paper_1911_07260_amd import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_FLAG_DEGREE_BINS,
-                                   OG_FLAG_HYBRID_DIRECTION, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, Schedule)
+import pytest
+
+from paper_1911_07260_amd import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ERR_HIP, OG_ERR_INTERNAL,
+                                   OG_ERR_INVALID_ARG, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE, OG_FLAG_DEGREE_BINS,
+                                   OG_FLAG_HYBRID_DIRECTION, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, OgError, Schedule)
 from paper_1911_07260_amd.autotune import Autotuner
 
 
@@ -28,14 +31,41 @@ def test_search_finds_synthetic_optimum():
     assert '"best_ms"' in js
 
 
-def test_failing_candidates_are_skipped():
+@pytest.mark.parametrize("status", [OG_ERR_WORKSPACE, OG_ERR_ROUND_LIMIT])
+def test_failing_candidates_are_skipped(status):
+    """A candidate whose queues overflow the workspace, or that runs out of
+    rounds, is a bad schedule: it is logged and the search goes on."""
     def runner(s):
         if s.update == OG_EAGER_NO_FUSION:
-            raise RuntimeError("queue overflow")
+            raise OgError(status, "og_sssp")
         return cost(s)
     res = Autotuner(runner).tune(weight_scale=15.0)
     assert res.best.update == OG_EAGER_WITH_FUSION
     assert any(not t.ok for t in res.trials)
+
+
+@pytest.mark.parametrize("status", [OG_ERR_INTERNAL, OG_ERR_HIP, OG_ERR_INVALID_ARG])
+def test_library_errors_propagate(status):
+    """A library bug (failed internal check), a HIP failure or an invalid
+    argument is not tuned around: it leaves tune() at once."""
+    calls = []
+
+    def runner(s):
+        calls.append(s)
+        if len(calls) == 3:
+            raise OgError(status, "og_sssp")
+        return cost(s)
+    with pytest.raises(OgError) as e:
+        Autotuner(runner).tune(weight_scale=15.0)
+    assert e.value.status == status
+    assert len(calls) == 3
+
+
+def test_other_exceptions_propagate():
+    def runner(s):
+        raise RuntimeError("not a library status")
+    with pytest.raises(RuntimeError):
+        Autotuner(runner).tune(weight_scale=15.0)
 
 
 def test_lazy_and_direction_candidates():
