@@ -135,6 +135,42 @@ typedef int32_t og_status;
                                OG_FLAG_LIGHT_HEAVY or a pull direction;
                                og_kcore ignores it.                           */
 
+#define OG_FLAG_VERTEX_BLOCKS 256u /* bucket fusion at the granularity of a
+                               vertex block (section 3.3: a worker keeps
+                               processing its share of the current bucket
+                               without a global synchronisation).  The library
+                               groups the vertices into compact blocks (cells
+                               of a hop-distance Voronoi partition from sampled
+                               seeds; about schedule.block_size vertices each,
+                               at most 4,096 vertices and 12,288 internal
+                               edges); a workgroup that takes a block holds its
+                               distances and internal edges (weights below
+                               65,536) in LDS and drains the block's part of
+                               the current bucket there, with LDS atomics; only
+                               edges that leave the block update dist in HBM.
+                               A block improved across its boundary in the
+                               current bucket is queued for any idle workgroup
+                               within the same round.  Meant for graphs with
+                               locality, such as road networks.  int32 weights,
+                               og_sssp / og_wbfs / og_ppsp / og_sssp_multi
+                               only (a batch or an A* estimate returns
+                               OG_ERR_INVALID_ARG), update
+                               OG_EAGER_WITH_FUSION and the persistent engine
+                               (else OG_ERR_INVALID_ARG), not together with
+                               OG_FLAG_LIGHT_HEAVY, OG_FLAG_DEGREE_BINS or a
+                               pull direction.  The workspace holds the blocked
+                               copy (about 20 bytes per vertex and 16 per edge),
+                               per-query block state and the build's
+                               temporaries (about 60 bytes per vertex); building
+                               the copy waits on the stream, also with
+                               OG_FLAG_ASYNC.  og_kcore ignores it.            */
+#define OG_FLAG_KEEP_BLOCKS 512u /* with OG_FLAG_VERTEX_BLOCKS: reuse the
+                               blocked copy that the previous block call on this
+                               workspace built, when it was for the same graph
+                               arrays, sizes and block_size (as
+                               OG_FLAG_KEEP_SPLIT; the caller promises that the
+                               graph's contents have not changed since).       */
+
 /* Priority-update strategies (section 4.2, configApplyPriorityUpdate). */
 #define OG_EAGER_NO_FUSION 0
 #define OG_EAGER_WITH_FUSION 1
@@ -188,6 +224,9 @@ typedef struct og_schedule {
   int32_t bin_wave;         /* OG_FLAG_DEGREE_BINS: largest degree relaxed by
                                one wavefront (0 = 64; below bin_thread: no
                                wavefront bin)                                 */
+  int32_t block_size;       /* OG_FLAG_VERTEX_BLOCKS: mean block size the
+                               partition aims at, in vertices (0 = 2048; at
+                               most 4096)                                     */
 } og_schedule;
 
 /* Per-call counters (host struct). */
@@ -214,6 +253,10 @@ typedef struct og_stats {
                                critical path in batch steps)                  */
   int64_t barriers;         /* device-wide synchronisations: one per round, two
                                with OG_LAZY_UPDATE                            */
+  int64_t blocks;           /* OG_FLAG_VERTEX_BLOCKS: blocks of the copy (the
+                               activations of blocks are counted in batches)  */
+  double prep_ms;           /* OG_FLAG_VERTEX_BLOCKS with OG_FLAG_TIMING: time
+                               to build the blocked copy (0 when kept)        */
 } og_stats;
 
 /* Library version, (major << 16) | minor. */
@@ -224,7 +267,7 @@ const char* og_status_string(og_status s);
 
 /* Overwrites every field of *s with the defaults (delta 1, fusion on,
  * threshold 1024, 16 window buckets, persistent engine, no limits, degree
- * bins 4 / 64). */
+ * bins 4 / 64, blocks of 2048 vertices). */
 og_status og_default_schedule(og_schedule* s);
 
 /* Workspace bytes og_sssp & co. need for this graph and schedule (0 if the
@@ -353,6 +396,15 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
  * (device) into *stats (host); used after an OG_FLAG_ASYNC call once the
  * stream has been synchronised.  Blocking copy on stream. */
 og_status og_read_stats(const void* ws, og_stats* stats, void* stream);
+
+/* Releases what the library keeps per host thread between calls: the HIP
+ * events of OG_FLAG_TIMING and the executable round graph of
+ * OG_ENGINE_GRAPH_ROUNDS (both are recreated on demand by a later call).
+ * Waits for the current device first.  Call it on each thread that made
+ * calls before that thread or the process ends, while the HIP runtime is
+ * still up (profilers attached to the process finalise in exit handlers).
+ * Returns OG_OK, or OG_ERR_HIP if a HIP call failed. */
+og_status og_release(void);
 
 #ifdef __cplusplus
 }

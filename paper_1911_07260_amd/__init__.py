@@ -17,7 +17,7 @@ The Schedule selects the update mode (eager with or without bucket fusion,
 lazy), the engine (persistent kernel, one launch per round, or rounds
 replayed from a captured hipGraph) and flags (structure validation, light /
 heavy edge split, dense-pull or hybrid traversal direction with lazy
-updates, degree-binned load balancing).  ``diff`` holds the FP32 forward and backward passes
+updates, degree-binned load balancing, LDS-resident vertex blocks).  ``diff`` holds the FP32 forward and backward passes
 (og_sssp_f32, og_sssp_backward_f32) and an autograd Function over them;
 ``autotune`` searches the schedule on the device (Delta, update strategy
 and direction, fusion threshold, window, workgroups, degree bins).
@@ -36,7 +36,8 @@ from . import _lib
 from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_GRAPH_ROUNDS, OG_ENGINE_HOST_ROUNDS,
                    OG_ENGINE_PERSISTENT, OG_ERR_HIP, OG_ERR_INTERNAL, OG_ERR_INVALID_ARG, OG_ERR_NEGATIVE_WEIGHT,
                    OG_ERR_OVERFLOW, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE, OG_FLAG_ASYNC, OG_FLAG_DEGREE_BINS,
-                   OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_KEEP_SPLIT, OG_FLAG_LIGHT_HEAVY, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_LAZY_UPDATE, OG_OK,
+                   OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_KEEP_BLOCKS, OG_FLAG_KEEP_SPLIT,
+                   OG_FLAG_LIGHT_HEAVY, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_FLAG_VERTEX_BLOCKS, OG_LAZY_UPDATE, OG_OK,
                    OgError, OgGraph, OgSchedule, OgStats)
 
 INF = 2**31 - 1
@@ -50,7 +51,8 @@ def _require(ok: bool, what: str) -> None:
 
 __all__ = [
     "DeviceGraph", "Schedule", "Workspace", "sssp", "wbfs", "ppsp", "astar", "sssp_batch", "ppsp_batch",
-    "astar_batch", "sssp_multi", "kcore", "workspace_bytes", "status_string", "version", "INF", "OgError",
+    "astar_batch", "sssp_multi", "kcore", "workspace_bytes", "status_string", "version", "release", "INF",
+    "OgError",
 ]
 
 
@@ -68,6 +70,7 @@ class Schedule:
     queue_capacity: int = 0
     bin_thread: int = 0
     bin_wave: int = 0
+    block_size: int = 0
 
     @property
     def fused(self) -> bool:
@@ -113,6 +116,15 @@ class DeviceGraph:
 
 def version() -> int:
     return int(_lib.load().og_version())
+
+
+def release() -> None:
+    """og_release: waits for the device and frees what the library keeps per
+    host thread (timing events, the replayed round graph)."""
+    lib = _lib.load()
+    status = lib.og_release()
+    if status != OG_OK:
+        raise OgError(status, "og_release", lib)
 
 
 def status_string(status: int) -> str:

@@ -29,6 +29,8 @@ OG_FLAG_DENSE_PULL = 16
 OG_FLAG_HYBRID_DIRECTION = 32
 OG_FLAG_DEGREE_BINS = 64
 OG_FLAG_KEEP_SPLIT = 128
+OG_FLAG_VERTEX_BLOCKS = 256
+OG_FLAG_KEEP_BLOCKS = 512
 
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1
@@ -72,6 +74,7 @@ class OgSchedule(ctypes.Structure):
         ("queue_capacity", ctypes.c_int64),
         ("bin_thread", ctypes.c_int32),
         ("bin_wave", ctypes.c_int32),
+        ("block_size", ctypes.c_int32),
     ]
 
 
@@ -95,6 +98,8 @@ class OgStats(ctypes.Structure):
         ("batches", ctypes.c_int64),
         ("chain", ctypes.c_int64),
         ("barriers", ctypes.c_int64),
+        ("blocks", ctypes.c_int64),
+        ("prep_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -166,6 +171,8 @@ def load():
     lib.og_workspace_bytes_kcore.argtypes = [P(OgGraph), P(OgSchedule)]
     lib.og_kcore.restype = i32
     lib.og_kcore.argtypes = [P(OgGraph), P(OgSchedule), vp, vp, ctypes.c_size_t, P(OgStats), vp]
+    lib.og_release.restype = i32
+    lib.og_release.argtypes = []
     lib.og_read_stats.restype = i32
     lib.og_read_stats.argtypes = [vp, P(OgStats), vp]
     _lib = lib

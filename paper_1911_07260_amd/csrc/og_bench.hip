@@ -183,6 +183,10 @@ int main(int argc, char** argv) {
               "\"reached_edges\": %.0f}\n",
               rmat ? "rmat" : "road", kcore ? "og_kcore" : "og_sssp", n, (long long)m, delta, update, engine, direction, steps,
               eng / steps, pred / steps, rounds / steps, tot_e / steps);
+  if (og_release() != OG_OK) {
+    std::fprintf(stderr, "og_release failed\n");
+    return 1;
+  }
   CHECK(hipStreamDestroy(stream));
   CHECK(hipFree(ws));
   CHECK(hipFree(d_rp));

@@ -185,6 +185,9 @@ struct Ctl {
   Word64 sym;          // symmetry checksum of OG_FLAG_VALIDATE with a pull direction
   Word slices;         // pull direction: row slices listed per copy of the graph
   Word64 pred_slices;  // predecessor pass: slices of long rows listed
+  Word blk_out;        // vertex blocks: work items of the round not yet finished
+  Word blk_head;       // vertex blocks: ring positions taken
+  Word blk_tail;       // vertex blocks: ring positions filled
 };
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block too large");
 
@@ -232,6 +235,24 @@ struct Args {
   int2* front;       // [n] pull, SSSP: (round stamp, distance) of the round's frontier vertices
   unsigned* fbits;   // [ceil(n / 32)] pull, k-core: bitmap of the vertices peeled in the round
   const int2* slices;  // pull: (base vertex, slice index) of every long row's slices
+  // vertex blocks (BlockW only); a block's vertices occupy positions
+  // bstart[b] .. bstart[b+1] of the blocked order
+  const int* bstart;     // [nb + 1]
+  const int4* bmeta;     // [nb] first position, vertices, first internal edge, internal edges
+  const int* verts;      // [n] vertex at each position
+  const int* blk_of;     // [n] block of each vertex
+  const int* irow;       // [n + 1] internal edges of each position (offsets into iedge)
+  const int* xrow;       // [n + 1] leaving edges of each position (offsets into xcol / xw / xblk)
+  const unsigned* iedge;  // internal edges: local target | weight << 16
+  const int* xcol;       // leaving edges: target vertex
+  const int* xw;         //                weight
+  const int* xblk;       //                target's block
+  int* brel;             // [n] per position: the distance at which the vertex's edges were last relaxed
+  unsigned* bstate;      // [nb] kBlkDirty / kBlkOwned
+  unsigned long long* ring;  // [ring_mask + 1] queue of dirty blocks: (position << 32) | (block + 1),
+                             // or (position << 32) once taken
+  unsigned ring_mask;
+  int nb;
 };
 
 struct Counters {
@@ -316,6 +337,7 @@ struct IntW {
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
   static constexpr bool kBin = false;
+  static constexpr bool kBlocks = false;
   // nd = d + w; false (and a status) for a negative weight or a sum that
   // reaches INT32_MAX
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
@@ -350,6 +372,7 @@ struct FloatW {
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
   static constexpr bool kBin = false;
+  static constexpr bool kBlocks = false;
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
     const float w = __int_as_float(wraw);
     if (!(w >= 0.0f) || w == __int_as_float(kInfBits)) {  // negative, NaN or infinite
@@ -424,6 +447,15 @@ struct BinFloatW : FloatW {
   static constexpr bool kBin = true;
 };
 
+// LDS-resident vertex blocks (bucket fusion at block granularity): the
+// vertices are grouped into compact blocks of at most kBcap vertices whose
+// distances, processed labels and internal edges a workgroup holds in LDS;
+// a block's part of the current bucket is drained there with LDS atomics,
+// and only edges leaving the block touch dist in HBM.  int32 distances.
+struct BlockW : IntW {
+  static constexpr bool kBlocks = true;
+};
+
 __device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
   int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
   return base + (size_t)index * a.cap;
@@ -457,8 +489,9 @@ __device__ int block_excl_scan(int x, Smem& s, int* total) {
 // lanes must call it together.  One atomic per wavefront and target reserves
 // the slots.  A full window slot or spill list falls back to the far list;
 // a full far list sets OG_ERR_WORKSPACE and drops the entry.
-__device__ void wave_push_global(const Args& a, const Smem& s, Counters& c, bool has, int tgt, int v,
-                                 int d, unsigned b) {
+template <class S>
+__device__ void wave_push_global(const Args& a, const S& s, Counters& c, bool has, int tgt, int v, int d,
+                                 unsigned b) {
   Ctl* ctl = a.ctl;
   const int K = a.K;
   for (;;) {
@@ -1818,12 +1851,17 @@ __device__ void decide(const Args& a) {
     st_dev(&c->c.hout, nhout);
   }
   if constexpr (W::kPull) st_dev(&c->c.pull, done ? 0u : pull_round(a, count));
+  if constexpr (W::kBlocks) {
+    st_dev(&c->blk_out.v, (unsigned)a.nwg);  // one input-scan token per workgroup
+    st_dev(&c->blk_head.v, 0u);              // ring positions restart
+    st_dev(&c->blk_tail.v, 0u);
+  }
   st_dev(&c->c.done, done);
   st_dev(&c->c.round, round);
 }
 
-template <class W>
-__device__ void load_control(const Args& a, Smem& s) {
+template <class W, class S>
+__device__ void load_control(const Args& a, S& s) {
   Ctl* c = a.ctl;
   s.cur = ld_dev(&c->c.cur);
   s.in_kind = (int)ld_dev(&c->c.in_kind);
@@ -1852,8 +1890,8 @@ __device__ void load_control(const Args& a, Smem& s) {
 // wave 0) publishes the new barrier count on kFlags release flags.  With
 // wait_others (the persistent engine) every other workgroup spins on one of
 // those flags; the host-driven engine ends the kernel instead.
-template <class W>
-__device__ void round_barrier(const Args& a, Smem& s, Counters& c, bool wait_others, bool decide_next) {
+template <class W, class S>
+__device__ void round_barrier(const Args& a, S& s, Counters& c, bool wait_others, bool decide_next) {
   Ctl* ctl = a.ctl;
   if (threadIdx.x == 0) atomicMax(&ctl->round_max_batches.v, c.round_batches);
   c.round_batches = 0;
@@ -2053,6 +2091,7 @@ __global__ void k_init_ctl(Args a) {
   c->far_tail[0].v = (unsigned)a.nsrc;
   c->far_min[1].v = kNoBucket;
   c->need.v = (unsigned)a.nsrc;
+  c->blk_out.v = (unsigned)a.nwg;  // vertex blocks: one input-scan token per workgroup
 }
 
 // Pull instantiations: the direction of the first round.
@@ -2209,6 +2248,821 @@ __global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
 __global__ __launch_bounds__(kBlock) void k_fill(int* p, long long n, int value) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) p[v] = value;
+}
+
+// ------------------------------------------------------------ vertex blocks
+//
+// Bucket fusion at the granularity of a vertex block (section 3.3: a worker
+// keeps processing its share of the current bucket without a global
+// synchronisation).  The vertices are grouped into compact blocks (at most
+// kBcap vertices and kEcap internal edges each); a workgroup that takes a
+// block loads its distances, its processed labels and its internal edges
+// into LDS and drains the block's part of the current bucket there: each
+// internal relaxation is an LDS atomic minimum, and an improved vertex of
+// the current bucket goes back on the block's LDS worklist at once.  Only
+// edges that leave the block touch dist in HBM.  An improvement across a
+// block boundary in the current bucket marks the target block dirty and
+// queues it in a device-wide ring of blocks, which idle workgroups serve
+// within the same round; one in a later bucket is filed in the window or
+// far list as usual.  A round ends when every work item of the round (one
+// input-scan token per workgroup, plus every queued block) is finished.
+//
+// Per-vertex state across activations: brel[p] is the distance at which the
+// vertex at position p last had its edges relaxed; the vertex is pending
+// when dist < brel.  Only the owner of a block reads or writes its brel
+// entries.  A block's state word holds kBlkDirty (queued, or changed while
+// owned) and kBlkOwned; a block is queued only on the transition from 0 to
+// dirty, so the ring holds each block at most once.
+constexpr int kBcap = 4096;   // vertices per block
+constexpr int kEcap = 12288;  // internal edges per block
+constexpr int kBwords = kBcap / 32;
+constexpr int kDefaultBlockSize = 2048;  // mean block size the clustering aims at
+constexpr int kIedgeWmax = 65536;        // an internal edge carries a 16-bit weight
+constexpr unsigned kBlkDirty = 1u, kBlkOwned = 2u;
+// Waits on the block ring give up after this many polls (seconds of
+// waiting, far beyond any round): the call then ends with OG_ERR_INTERNAL
+// instead of hanging on a broken invariant.
+constexpr unsigned kBlkSpinLimit = 1u << 23;
+
+struct BlkSmem {
+  int dist[kBcap];   // distances of the block's vertices
+  int rel[kBcap];    // distance at which each vertex's edges were last relaxed
+  int orig[kBcap];   // distances as loaded (the write-back sends what fell below them)
+  int vert[kBcap];   // vertex id of each local index
+  int xrow[kBcap + 1];   // leaving-edge offsets into xcol / xw / xblk
+  unsigned edge[kEcap];  // internal edges: local target | weight << 16
+  unsigned short row[kBcap + 2];  // internal-edge offsets (the +2 keeps the next array aligned)
+  unsigned short wl[kBcap];  // worklist ring of local indices; after a drain, the list of
+                             // relaxed vertices with leaving edges
+  unsigned prc[kBwords];     // edges relaxed in this drain
+  unsigned wl_head, wl_tail;
+  int xn;
+  int claim, again, ok, nv, p0, e0, ne;
+  // control snapshot (the fields load_control, round_barrier and
+  // wave_push_global use)
+  unsigned cur, in_count, win_hi, round, epoch, far_stamp;
+  int in_kind, in_index, done, spill_out, far_out;
+  int hout;
+  unsigned hgen;
+  int pull;
+  int last, exhausted, mode, nb;
+  unsigned gbase;
+};
+
+// Ring slots carry the position they were filled for, so a ticket never
+// takes another lap's entry: slot p % size holds (p << 32) | (block + 1)
+// while queued and (p << 32) once taken.
+__device__ __forceinline__ unsigned long long ld_slot(const unsigned long long* q) {
+  return __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_slot(unsigned long long* q, unsigned long long x) {
+  __hip_atomic_store(q, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Marks block b dirty; on the transition from clean it becomes a work item
+// of the round and is queued.  The caller holds a work item itself, so the
+// round cannot end in between; the count is raised before the block can be
+// taken (and so finished and counted down).  The slot's previous entry (a
+// lap earlier) has been taken unless its ticket holder is still reading it.
+__device__ void blk_mark(const Args& a, int b) {
+  const unsigned old = atomicOr(a.bstate + b, kBlkDirty);
+  if (old & (kBlkDirty | kBlkOwned)) return;
+  atomicAdd(&a.ctl->blk_out.v, 1u);
+  const unsigned pos = atomicAdd(&a.ctl->blk_tail.v, 1u);
+  wait_vm();
+  unsigned long long* slot = a.ring + (pos & a.ring_mask);
+  for (unsigned spin = 0; (unsigned)ld_slot(slot) != 0u; ++spin) {
+    if (spin == kBlkSpinLimit) {
+      set_status(a.ctl, OG_ERR_INTERNAL);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  st_slot(slot, ((unsigned long long)pos << 32) | (unsigned)(b + 1));
+}
+
+// Takes a queued block (thread 0 of a workgroup): draws the next ticket
+// (ring position) and waits for the block pushed at that position; -1 once
+// no work item of the round is left (that position is then never filled:
+// every pushed block is counted until it is finished).  Positions start
+// from 0 each round (reset by the bucket decision).
+__device__ int blk_pop(const Args& a) {
+  Ctl* c = a.ctl;
+  const unsigned t = atomicAdd(&c->blk_head.v, 1u);
+  unsigned long long* slot = a.ring + (t & a.ring_mask);
+  int nap = 1;
+  for (unsigned polls = 0;; ++polls) {
+    if (polls == kBlkSpinLimit) {
+      set_status(c, OG_ERR_INTERNAL);
+      return -1;
+    }
+    const unsigned long long x = ld_slot(slot);
+    if ((unsigned)(x >> 32) == t && (unsigned)x != 0u) {
+      st_slot(slot, (unsigned long long)t << 32);
+      return (int)((unsigned)x - 1u);
+    }
+    if (ld_dev(&c->blk_out.v) == 0u) return -1;
+    for (int k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(4);
+    nap = nap < 8 ? 2 * nap : 8;
+  }
+}
+
+// Appends local index j of the lanes with push to the worklist (all 64
+// lanes call it together; one LDS atomic per wavefront).
+__device__ __forceinline__ void blk_wl_push(BlkSmem& s, bool push, int j) {
+  const unsigned long long m = __ballot(push);
+  if (m == 0) return;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(&s.wl_tail, (unsigned)__popcll(m));
+  base = __shfl(base, leader);
+  if (push) s.wl[(base + (unsigned)__popcll(m & lanemask_lt())) & (unsigned)(kBcap - 1)] = (unsigned short)j;
+}
+
+__device__ __forceinline__ int blk_window_target(const Args& a, const BlkSmem& s, bool has, unsigned bk) {
+  return has ? (bk < s.win_hi ? (int)(bk & (unsigned)(a.K - 1)) : a.K + 1) : 0;
+}
+
+// Internal edges a lane relaxes together in a drain step.
+constexpr int kBlkIlp = 4;
+
+// Drains the block's worklist in LDS.  A vertex is on the worklist exactly
+// while it is pending in the current bucket (dist < rel and bucket(dist) <=
+// current), so the ring never holds more than the block's vertices.  Each
+// step takes up to kBlock entries, one per lane: the lane publishes rel =
+// dist for its vertex before a barrier, then relaxes the vertex's internal
+// edges with LDS atomic minima; an improvement queues its target when that
+// makes the target pending (it was not, or only in a later bucket).
+// Leaving edges wait for the end of the drain (blk_leave_and_write).  (A
+// lane-level chase, one lane following a chain of improvements without
+// barriers, relaxed 2.2-2.5 times as many edges on the road grid and was
+// twice as slow.)
+template <class W>
+__device__ void blk_drain(const Args& a, BlkSmem& s, Counters& c, unsigned cur) {
+  const int tid = threadIdx.x;
+  unsigned n_relax = 0, n_improve = 0, n_push = 0;  // (32-bit: few registers in the loop)
+  for (;;) {
+    __syncthreads();  // the previous step's pushes are in place
+    const unsigned h = s.wl_head, t = s.wl_tail;
+    if (h == t) break;
+    const unsigned nb = t - h < (unsigned)kBlock ? t - h : (unsigned)kBlock;
+    int d = 0, k0 = 0, k1 = 0;
+    if ((unsigned)tid < nb) {
+      const int i = s.wl[(h + (unsigned)tid) & (unsigned)(kBcap - 1)];
+      d = s.dist[i];
+      if (d < s.rel[i]) {
+        s.rel[i] = d;
+        atomicOr(&s.prc[i >> 5], 1u << (i & 31));
+        k0 = s.row[i];
+        k1 = s.row[i + 1];
+      }
+    }
+    __syncthreads();  // ring pointers read, the step's rel values published
+    if (tid == 0) s.wl_head = h + nb;
+    for (int k = k0; __ballot(k < k1) != 0; k += kBlkIlp) {
+      int j[kBlkIlp], nd[kBlkIlp];
+      bool go[kBlkIlp];
+#pragma unroll
+      for (int q = 0; q < kBlkIlp; ++q) {
+        go[q] = k + q < k1;
+        j[q] = 0;
+        nd[q] = 0;
+        if (go[q]) {
+          const unsigned e = s.edge[k + q];
+          j[q] = (int)(e & 0xffffu);
+          n_relax++;
+          go[q] = W::add(a, d, (int)(e >> 16), &nd[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kBlkIlp; ++q)
+        if (go[q]) go[q] = nd[q] < s.dist[j[q]];
+      bool push[kBlkIlp];
+#pragma unroll
+      for (int q = 0; q < kBlkIlp; ++q) {
+        push[q] = false;
+        if (go[q]) {
+          const int old = atomicMin(&s.dist[j[q]], nd[q]);
+          if (nd[q] < old) {
+            n_improve++;
+            push[q] = W::bucket(a, (unsigned)nd[q]) <= cur &&
+                      (old >= s.rel[j[q]] || W::bucket(a, (unsigned)old) > cur);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kBlkIlp; ++q) {
+        if (push[q]) n_push++;
+        blk_wl_push(s, push[q], j[q]);
+      }
+    }
+  }
+  c.relax += n_relax;
+  c.improve += n_improve;
+  c.push_local += n_push;
+}
+
+// After a drain: the leaving edges of the vertices it relaxed, each at the
+// vertex's final distance, all in flight together; and the write-back of
+// every distance the drain lowered (one device-scope atomic minimum per
+// vertex, filed in its later bucket when that improves it) and of the
+// relaxed labels.  An improvement across the boundary in the current bucket
+// marks the target block.
+template <class W>
+__device__ void blk_leave_and_write(const Args& a, BlkSmem& s, Counters& c, unsigned cur) {
+  constexpr int kPer = kBcap / kBlock;
+  const int tid = threadIdx.x;
+  const int nv = s.nv, p0 = s.p0;
+  if (tid == 0) s.xn = 0;
+  __syncthreads();  // (the drain ended on a barrier: the ring is free for the list)
+  // write-back atomics first: their round trips overlap the leaving edges'
+  int old[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = q * kBlock + tid;
+    old[q] = -1;
+    if (i < nv && s.dist[i] < s.orig[i]) old[q] = atomicMin(&a.dist[s.vert[i]], s.dist[i]);
+  }
+  for (int base = 0; base < nv; base += kBlock) {
+    const int i = base + tid;
+    bool lx = false;
+    if (i < nv && ((s.prc[i >> 5] >> (i & 31)) & 1u)) {
+      st_dev(reinterpret_cast<unsigned*>(a.brel) + p0 + i, (unsigned)s.rel[i]);
+      lx = s.xrow[i + 1] > s.xrow[i];
+    }
+    const unsigned long long m = __ballot(lx);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      int pos = 0;
+      if ((int)lane_id() == leader) pos = atomicAdd(&s.xn, __popcll(m));
+      pos = __shfl(pos, leader);
+      if (lx) s.wl[pos + __popcll(m & lanemask_lt())] = (unsigned short)i;
+    }
+  }
+  __syncthreads();
+  const int xn = s.xn;
+  for (int base = 0; base < xn; base += kBlock) {
+    int x0 = 0, x1 = 0, d = 0;
+    if (base + tid < xn) {
+      const int i = s.wl[base + tid];
+      x0 = s.xrow[i];
+      x1 = s.xrow[i + 1];
+      d = s.rel[i];
+    }
+    for (int k = x0; __ballot(k < x1) != 0; ++k) {
+      bool has = false;
+      int u = 0, nd = 0;
+      unsigned bk = 0;
+      if (k < x1) {
+        u = a.xcol[k];
+        const int w = a.xw[k];
+        c.relax++;
+        if (W::add(a, d, w, &nd)) {
+          const int o = atomicMin(&a.dist[u], nd);
+          if (nd < o) {
+            c.improve++;
+            bk = W::bucket(a, (unsigned)nd);
+            if (bk <= cur) blk_mark(a, a.xblk[k]);
+            else has = true;
+          }
+        }
+      }
+      wave_push_global(a, s, c, has, blk_window_target(a, s, has, bk), u, nd, bk);
+    }
+  }
+  // the write-back's results: an improvement into a later bucket is filed
+  // there (one in the current bucket was relaxed in the drain)
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (q * kBlock >= nv) break;
+    const int i = q * kBlock + tid;
+    bool has = false;
+    int v = 0, nd = 0;
+    unsigned bk = 0;
+    if (i < nv && old[q] >= 0) {
+      nd = s.dist[i];
+      if (nd < old[q]) {
+        v = s.vert[i];
+        bk = W::bucket(a, (unsigned)nd);
+        has = bk > cur;
+      }
+    }
+    wave_push_global(a, s, c, has, blk_window_target(a, s, has, bk), v, nd, bk);
+  }
+  wait_vm();  // the block's results are in HBM before it can be released
+}
+
+// One activation of block b (taken from the ring): load it, then drain,
+// relax its leaving edges and write back until no other workgroup has
+// changed it meanwhile.
+template <class W>
+__device__ void blk_process(const Args& a, BlkSmem& s, Counters& c, int b) {
+  constexpr int kPer = kBcap / kBlock, kPerE = kEcap / kBlock;
+  const int tid = threadIdx.x;
+  const unsigned cur = s.cur;
+  if (tid == 0) {
+    int ok = (unsigned)b < (unsigned)a.nb;
+    int4 mt = make_int4(0, 0, 0, 0);
+    if (ok) {
+      const unsigned st = atomicCAS(a.bstate + b, kBlkDirty, kBlkOwned);
+      mt = a.bmeta[b];  // issued together with the claim
+      ok = st == kBlkDirty && mt.y >= 1 && mt.y <= kBcap && mt.w >= 0 && mt.w <= kEcap;
+    }
+    if (!ok) set_status(a.ctl, OG_ERR_INTERNAL);
+    s.ok = ok;
+    s.p0 = mt.x;
+    s.nv = mt.y;
+    s.e0 = mt.z;
+    s.ne = mt.w;
+  }
+  __syncthreads();
+  if (!s.ok) return;
+  const int nv = s.nv, p0 = s.p0, ne = s.ne, e0 = s.e0;
+  {
+    // the block's loads in groups of kLoadGroup per thread, each group's
+    // loads in flight together
+    constexpr int kLoadGroup = 4;
+    for (int q0 = 0; q0 < kPer; q0 += kLoadGroup) {
+      if (q0 * kBlock >= nv) break;
+      int vv[kLoadGroup], rr[kLoadGroup], ro[kLoadGroup], xr[kLoadGroup];
+#pragma unroll
+      for (int q = 0; q < kLoadGroup; ++q) {
+        const int i = (q0 + q) * kBlock + tid;
+        vv[q] = rr[q] = ro[q] = xr[q] = 0;
+        if (i < nv) {
+          vv[q] = a.verts[p0 + i];
+          rr[q] = (int)ld_dev(reinterpret_cast<const unsigned*>(a.brel) + p0 + i);
+          ro[q] = a.irow[p0 + i];
+          xr[q] = a.xrow[p0 + i];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kLoadGroup; ++q) {
+        const int i = (q0 + q) * kBlock + tid;
+        if (i < nv) {
+          s.vert[i] = vv[q];
+          s.rel[i] = rr[q];
+          s.row[i] = (unsigned short)(ro[q] - e0);
+          s.xrow[i] = xr[q];
+        }
+      }
+    }
+    constexpr int kEdgeGroup = 8;
+    for (int q0 = 0; q0 < kPerE; q0 += kEdgeGroup) {
+      if (q0 * kBlock >= ne) break;
+      unsigned ev[kEdgeGroup];
+#pragma unroll
+      for (int q = 0; q < kEdgeGroup; ++q) {
+        const int k = (q0 + q) * kBlock + tid;
+        ev[q] = k < ne ? a.iedge[e0 + k] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < kEdgeGroup; ++q) {
+        const int k = (q0 + q) * kBlock + tid;
+        if (k < ne) s.edge[k] = ev[q];
+      }
+    }
+    if (tid == 0) {
+      s.row[nv] = (unsigned short)ne;
+      s.xrow[nv] = a.xrow[p0 + nv];
+    }
+  }
+  for (;;) {
+    for (int k = tid; k < kBwords; k += kBlock) s.prc[k] = 0u;
+    __syncthreads();
+    // the current distances: device-scope loads see every other
+    // workgroup's atomic minimum that completed before it marked the block
+    for (int q0 = 0; q0 < kPer; q0 += 8) {
+      if (q0 * kBlock >= nv) break;
+      int dd[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = (q0 + q) * kBlock + tid;
+        dd[q] = i < nv ? (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + s.vert[i]) : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = (q0 + q) * kBlock + tid;
+        if (i < nv) {
+          s.dist[i] = dd[q];
+          s.orig[i] = dd[q];
+        }
+      }
+    }
+    if (tid == 0) s.wl_head = s.wl_tail = 0u;
+    __syncthreads();
+    // the block's pending vertices of the current bucket start the worklist
+    for (int base = 0; base < nv; base += kBlock) {
+      const int i = base + tid;
+      bool push = false;
+      if (i < nv) {
+        const int d = s.dist[i];
+        push = d < s.rel[i] && W::bucket(a, (unsigned)d) <= cur;
+      }
+      blk_wl_push(s, push, i);
+    }
+    blk_drain<W>(a, s, c, cur);
+    blk_leave_and_write<W>(a, s, c, cur);
+    __syncthreads();
+    if (tid == 0) {
+      int again = 0;
+      if (atomicCAS(a.bstate + b, kBlkOwned, 0u) != kBlkOwned) {  // dirtied while owned
+        atomicExch(a.bstate + b, kBlkOwned);
+        again = 1;
+      }
+      s.again = again;
+    }
+    __syncthreads();
+    if (!s.again) break;
+  }
+}
+
+// One round of the block engine: scan the round input (one chunk at a time,
+// as run_round) and mark the blocks of its live entries, give back the
+// scan token, then serve queued blocks until the round's work is done.
+template <class W>
+__device__ void run_round_blocks(const Args& a, BlkSmem& s, Counters& c) {
+  const int tid = threadIdx.x;
+  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const unsigned count = s.in_count;
+  const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
+  const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
+  const unsigned cur = s.cur;
+  if (tid == 0) s.exhausted = 0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) {
+      s.mode = 0;
+      if (!s.exhausted) {
+        unsigned base;
+        if (fixed) {
+          base = (unsigned)blockIdx.x * per;
+          s.exhausted = 1;
+        } else {
+          base = atomicAdd(&a.ctl->in_head.v, (unsigned)kBlock);
+        }
+        if (base < count) {
+          s.mode = 2;
+          const unsigned left = count - base;
+          s.nb = (int)(left < per ? left : per);
+          s.gbase = base;
+        } else {
+          s.exhausted = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (s.mode == 0) break;
+    int v = -1, d = 0;
+    if (tid < s.nb) {
+      const int2 e = ld_entry(in, (size_t)s.gbase + tid);
+      v = e.x;
+      d = e.y;
+      if ((unsigned)v >= (unsigned)a.n) {
+        set_status(a.ctl, OG_ERR_INTERNAL);
+        v = -1;
+      }
+    }
+    bool repush = false, live = false;
+    unsigned rb = 0;
+    if (v >= 0 && d <= a.dist[v]) {
+      rb = W::bucket(a, W::key(a, v, d));
+      if (rb > cur) repush = true;  // a far-list entry of a later bucket
+      else live = true;
+    }
+    wave_push_global(a, s, c, repush, blk_window_target(a, s, repush, rb), v, d, rb);
+    if (live) blk_mark(a, a.blk_of[v]);
+  }
+  if (tid == 0) atomicSub(&a.ctl->blk_out.v, 1u);  // the scan token (every wave's marks are complete)
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s.claim = blk_pop(a);
+    __syncthreads();
+    const int b = s.claim;
+    if (b < 0) break;
+    blk_process<W>(a, s, c, b);
+    __syncthreads();
+    if (tid == 0) {
+      wait_vm();
+      atomicSub(&a.ctl->blk_out.v, 1u);
+    }
+    c.batches++;
+    c.round_batches++;
+  }
+}
+
+// Persistent block engine: rounds separated by the device-wide barrier
+// whose last arriver takes the bucket decision (as k_persistent).
+template <class W>
+__global__ __launch_bounds__(kBlock) void k_blocks(Args a) {
+  __shared__ BlkSmem s;
+  Counters c;
+  if (threadIdx.x == 0) load_control<W>(a, s);
+  __syncthreads();
+  while (!s.done) {
+    run_round_blocks<W>(a, s, c);
+    round_barrier<W>(a, s, c, true, true);
+    if (threadIdx.x == 0) load_control<W>(a, s);
+    __syncthreads();
+  }
+  flush_counters(a, c);
+}
+
+// ---- building the blocked copy
+//
+// Blocks are the cells of a graph Voronoi partition: seeds are sampled
+// (rate 1 / block_size), every vertex takes the seed nearest to it in hops
+// (ties to the smaller seed id, so the partition is unique), found by a
+// level-synchronous multi-source BFS along out-edges.  A cell with more than
+// kBcap vertices or kEcap internal edges is split by re-running the BFS over
+// it from two seeds, its old one and its farthest vertex; vertices no seed
+// reaches are sampled again at a higher rate.  A label packs (hops << 32 |
+// seed).
+constexpr unsigned long long kNoLab = ~0ull;
+
+__device__ __forceinline__ unsigned long long cl_lab(unsigned hop, int v) {
+  return ((unsigned long long)hop << 32) | (unsigned)v;
+}
+__device__ __forceinline__ int cl_seed(unsigned long long l) { return (int)(unsigned)(l & 0xffffffffull); }
+// 32-bit integer hash (the finaliser of MurmurHash3)
+__device__ __forceinline__ unsigned cl_hash(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  return x ^ (x >> 16);
+}
+__device__ __forceinline__ bool cl_internal(int v, int u, int w, int bv, int bu) {
+  return u != v && bu == bv && w >= 0 && w < kIedgeWmax;
+}
+
+// Which vertices this pass labels (fr = 1) and its seeds: unlabelled
+// vertices are sampled at 1 / rate.  A vertex of an oversized cell is
+// reset; the cell's seed and its farthest vertex stay seeds, and more are
+// sampled in it, about twice as many as the pieces it must be cut into,
+// doubled on every further pass (from pass 17 on every vertex is a seed,
+// and a one-vertex cell is never oversized, so the passes end).
+__global__ __launch_bounds__(kBlock) void k_cl_prep(int n, unsigned long long* lab, int* fr, const int* over,
+                                                     const unsigned long long* far, const int* cnt, const int* ecnt,
+                                                     unsigned rate, int target, int pass, unsigned salt) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    unsigned long long l = pass == 0 ? kNoLab : lab[v];
+    int f = 0;
+    if (l == kNoLab) {
+      f = 1;
+      l = cl_hash((unsigned)v ^ salt) % rate == 0u ? cl_lab(0, (int)v) : kNoLab;
+    } else {
+      const int sd = cl_seed(l);
+      if (over[sd]) {
+        f = 1;
+        const long long c = cnt[sd], pieces_v = (c + target - 1) / target,
+                        pieces_e = ((long long)ecnt[sd] + kEcap / 2 - 1) / (kEcap / 2);
+        long long dens = (pieces_v > pieces_e ? pieces_v : pieces_e) * 2;
+        dens <<= (pass < 16 ? pass : 16);
+        const unsigned r = c / dens > 1 ? (unsigned)(c / dens) : 1u;
+        l = (v == sd || v == cl_seed(far[sd]) || cl_hash((unsigned)v ^ salt) % r == 0u) ? cl_lab(0, (int)v) : kNoLab;
+      }
+    }
+    lab[v] = l;
+    fr[v] = f;
+  }
+}
+
+// One BFS level over the vertices being labelled: a vertex at `level` hops
+// offers (level + 1, its seed) to its free out-neighbours.
+__global__ __launch_bounds__(kBlock) void k_cl_bfs(int n, const long long* row_ptr, const int* col,
+                                                    unsigned long long* lab, const int* fr, unsigned level,
+                                                    unsigned* changed) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  bool any = false;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    if (!fr[v]) continue;
+    const unsigned long long l = lab[v];
+    if (l == kNoLab || (unsigned)(l >> 32) != level) continue;
+    const unsigned long long cand = cl_lab(level + 1u, cl_seed(l));
+    for (long long e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      const int u = col[e];
+      if (u == v || !fr[u] || cand >= lab[u]) continue;
+      if (atomicMin(&lab[u], cand) > cand) any = true;
+    }
+  }
+  if (__ballot(any) != 0 && lane_id() == 0) atomicAdd(changed, 1u);
+}
+
+// Cell sizes, internal edge counts and each cell's farthest vertex.
+__global__ __launch_bounds__(kBlock) void k_cl_count(int n, const long long* row_ptr, const int* col, const int* w,
+                                                      const unsigned long long* lab, int* cnt, int* ecnt,
+                                                      unsigned long long* far) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const unsigned long long l = lab[v];
+    if (l == kNoLab) continue;
+    const int sd = cl_seed(l);
+    atomicAdd(&cnt[sd], 1);
+    int k = 0;
+    for (long long e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      const int u = col[e];
+      const unsigned long long lu = lab[u];
+      if (lu != kNoLab && cl_internal((int)v, u, w[e], sd, cl_seed(lu))) ++k;
+    }
+    if (k) atomicAdd(&ecnt[sd], k);
+    atomicMax(&far[sd], ((l >> 32) << 32) | (unsigned long long)v);
+  }
+}
+
+// Oversized cells (flagged by seed) and the vertices still unlabelled.
+__global__ __launch_bounds__(kBlock) void k_cl_over(int n, const unsigned long long* lab, const int* cnt,
+                                                     const int* ecnt, int* over, unsigned* flags) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  bool o_any = false, u_any = false;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const bool o = cnt[v] > kBcap || ecnt[v] > kEcap;
+    over[v] = o ? 1 : 0;
+    o_any |= o;
+    u_any |= lab[v] == kNoLab;
+  }
+  if (__ballot(o_any) != 0 && lane_id() == 0) atomicAdd(&flags[0], 1u);
+  if (__ballot(u_any) != 0 && lane_id() == 0) atomicAdd(&flags[1], 1u);
+}
+
+// seed flags (a seed is the only vertex at hop 0 of its own cell)
+__global__ __launch_bounds__(kBlock) void k_cl_isseed(int n, const unsigned long long* lab, int* flag) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride)
+    flag[v] = v < n && lab[v] == cl_lab(0, (int)v) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cl_assign(int n, const unsigned long long* lab, const int* bid,
+                                                       int* blk_of, int* bsize) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int b = bid[cl_seed(lab[v])];
+    blk_of[v] = b;
+    atomicAdd(&bsize[b], 1);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cl_scatter(int n, const int* blk_of, const int* bstart, int* fill,
+                                                        int* verts) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int b = blk_of[v];
+    verts[bstart[b] + atomicAdd(&fill[b], 1)] = (int)v;
+  }
+}
+
+// Each block's vertices in increasing id order (bitonic sort in LDS, one
+// workgroup per block), so that the blocked order does not depend on the
+// order of the scatter's atomics.
+__global__ __launch_bounds__(kBlock) void k_cl_sort(int nb, const int* bstart, int* verts) {
+  __shared__ int key[kBcap];
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int p0 = bstart[b], nv = bstart[b + 1] - p0;
+    if (nv > kBcap) continue;  // never built (the engine reports such a block as internal)
+    int np = 1;
+    while (np < nv) np <<= 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += kBlock) key[i] = i < nv ? verts[p0 + i] : INT_MAX;
+    for (int k = 2; k <= np; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < np; i += kBlock) {
+          const int l = i ^ j;
+          if (l > i) {
+            const int x = key[i], y = key[l];
+            if (((i & k) == 0) == (x > y)) {
+              key[i] = y;
+              key[l] = x;
+            }
+          }
+        }
+      }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += kBlock) verts[p0 + i] = key[i];
+  }
+}
+
+// Per block: first position, vertices, first internal edge, internal edges.
+__global__ __launch_bounds__(kBlock) void k_cl_meta(int nb, const int* bstart, const int* irow, int4* bmeta) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+    const int p0 = bstart[b], p1 = bstart[b + 1];
+    bmeta[b] = make_int4(p0, p1 - p0, irow[p0], irow[p1] - irow[p0]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cl_pos(int n, const int* verts, int* pos) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) pos[verts[p]] = (int)p;
+}
+
+// Internal and leaving edges of the vertex at each position.
+__global__ __launch_bounds__(kBlock) void k_cl_ecount(int n, const long long* row_ptr, const int* col, const int* w,
+                                                       const int* verts, const int* blk_of, int* icnt, int* xcnt) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p <= n; p += stride) {
+    int ki = 0, kx = 0;
+    if (p < n) {
+      const int v = verts[p], b = blk_of[v];
+      for (long long e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        const int u = col[e];
+        if (cl_internal(v, u, w[e], b, blk_of[u])) ++ki;
+        else ++kx;
+      }
+    }
+    icnt[p] = ki;
+    xcnt[p] = kx;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cl_efill(int n, const long long* row_ptr, const int* col, const int* w,
+                                                      const int* verts, const int* blk_of, const int* pos,
+                                                      const int* bstart, const int* irow, const int* xrow,
+                                                      unsigned* iedge, int* xcol, int* xw, int* xblk) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const int v = verts[p], b = blk_of[v];
+    int ki = irow[p], kx = xrow[p];
+    for (long long e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      const int u = col[e], wt = w[e], bu = blk_of[u];
+      if (cl_internal(v, u, wt, b, bu)) {
+        iedge[ki++] = (unsigned)(pos[u] - bstart[b]) | ((unsigned)wt << 16);
+      } else {
+        xcol[kx] = u;
+        xw[kx] = wt;
+        xblk[kx] = bu;
+        ++kx;
+      }
+    }
+  }
+}
+
+// Exclusive prefix sum of n ints in tiles of kScanTile: per-tile scans with
+// their totals, a scan of the totals by one workgroup, then the tile
+// offsets added.
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__device__ int blk_scan_excl(int x, int* wsum, int* total) {
+  const int lane = (int)lane_id(), wid = threadIdx.x / kWave;
+  int v = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = v;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    const int t = wsum[i];
+    pre += i < wid ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + v - x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const int* in, int* out, long long n, int* tile_sum) {
+  __shared__ int wsum[kWaves];
+  const long long t0 = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
+  int x[kScanPer];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    x[k] = t0 + k < n ? in[t0 + k] : 0;
+    sum += x[k];
+  }
+  int total;
+  int run = blk_scan_excl(sum, wsum, &total);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (t0 + k < n) out[t0 + k] = run;
+    run += x[k];
+  }
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums(int* tile_sum, int ntiles) {
+  __shared__ int wsum[kWaves];
+  int carry = 0;
+  for (int base = 0; base < ntiles; base += kBlock) {
+    const int i = base + (int)threadIdx.x;
+    const int x = i < ntiles ? tile_sum[i] : 0;
+    int total;
+    const int e = blk_scan_excl(x, wsum, &total);
+    if (i < ntiles) tile_sum[i] = carry + e;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(int* out, long long n, const int* tile_sum) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] += tile_sum[i / kScanTile];
 }
 
 // Parity summary of the final distances for the predecessor pass: bit
@@ -2482,6 +3336,7 @@ struct DeviceInfo {
   int occ_core_pull = 0;  // co-resident k_persistent<CorePullW> workgroups per CU
   int occ_bin = 0;    // co-resident k_persistent<BinW> workgroups per CU
   int occ_bin_float = 0;  // co-resident k_persistent<BinFloatW> workgroups per CU
+  int occ_blocks = 0;  // co-resident k_blocks<BlockW> workgroups per CU
   int coop = 0;
   bool valid = false;
 };
@@ -2514,6 +3369,8 @@ bool device_info(int dev, DeviceInfo* out) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_bin_float, k_persistent<BinFloatW>, kBlock, 0) !=
         hipSuccess)
       return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&di.occ_blocks, k_blocks<BlockW>, kBlock, 0) != hipSuccess)
+      return false;
     di.valid = true;
   }
   *out = di;
@@ -2537,11 +3394,13 @@ struct SplitKey {
   const void* col;
   const void* w;
   long long n, m;
-  unsigned delta;
+  unsigned delta;  // the split's Delta, or the blocked copy's target block size
   const void* copy;
+  int kind;           // 0: light/heavy split copy, 1: blocked copy
+  long long nb = 0;   // blocked copy: its block count (not part of the match)
   bool operator==(const SplitKey& o) const {
     return ws == o.ws && row_ptr == o.row_ptr && col == o.col && w == o.w && n == o.n && m == o.m &&
-           delta == o.delta && copy == o.copy;
+           delta == o.delta && copy == o.copy && kind == o.kind;
   }
 };
 std::mutex g_split_mu;
@@ -2554,9 +3413,12 @@ void forget_split(const void* ws) {
                      g_split_keys.end());
 }
 
-bool split_kept(const SplitKey& key) {
+bool split_kept(const SplitKey& key, long long* nb = nullptr) {
   std::lock_guard<std::mutex> lk(g_split_mu);
-  return std::find(g_split_keys.begin(), g_split_keys.end(), key) != g_split_keys.end();
+  const auto it = std::find(g_split_keys.begin(), g_split_keys.end(), key);
+  if (it == g_split_keys.end()) return false;
+  if (nb) *nb = it->nb;
+  return true;
 }
 
 void record_split(const SplitKey& key) {
@@ -2568,16 +3430,26 @@ void record_split(const SplitKey& key) {
   g_split_keys.push_back(key);
 }
 
-// Per-thread HIP events for OG_FLAG_TIMING (created on first use).
+// Per-thread HIP events for OG_FLAG_TIMING (created on first use, destroyed
+// by og_release).
 struct Timers {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool ok = false;
   bool init() {
     if (ok) return true;
     for (auto& e : ev)
-      if (hipEventCreate(&e) != hipSuccess) return false;
+      if (!e && hipEventCreate(&e) != hipSuccess) return false;
     ok = true;
     return true;
+  }
+  bool release() {
+    bool good = true;
+    for (auto& e : ev) {
+      if (e && hipEventDestroy(e) != hipSuccess) good = false;
+      e = nullptr;
+    }
+    ok = false;
+    return good;
   }
 };
 thread_local Timers t_timers;
@@ -2591,6 +3463,8 @@ og_schedule resolved(const og_schedule* s) {
   if (r.bin_thread == 0) r.bin_thread = kBinLane;
   if (r.bin_thread > kBinLane) r.bin_thread = kBinLane;
   if (r.bin_wave == 0) r.bin_wave = kDefaultBinWave;
+  if (r.block_size <= 0) r.block_size = kDefaultBlockSize;
+  if (r.block_size > kBcap) r.block_size = kBcap;
   r.window_buckets = pow2_at_least(r.window_buckets < 2 ? 2 : r.window_buckets);
   return r;
 }
@@ -2620,6 +3494,59 @@ size_t table_bytes(const Shape& sh) {
 }
 
 bool split_on(const og_schedule* r, const Shape& sh) { return !sh.core && (r->flags & OG_FLAG_LIGHT_HEAVY); }
+bool blocks_on(const og_schedule* r, const Shape& sh) { return !sh.core && (r->flags & OG_FLAG_VERTEX_BLOCKS); }
+
+// Workspace regions of the vertex-block engine, from byte offset off: the
+// blocked copy (kept across calls with OG_FLAG_KEEP_BLOCKS), the per-query
+// state, and the temporaries of building the copy.
+struct BlkLayout {
+  size_t bstart, bmeta, verts, blk_of, irow, xrow, iedge, xcol, xw, xblk;  // blocked copy
+  size_t brel, bstate, ring;                                         // per query
+  size_t lab, fr, cnt, ecnt, far, over, flag, bsize, fill, pos, icnt, xcnt, tiles, flags;  // build
+  size_t end;
+  unsigned long long ring_cap;
+};
+
+BlkLayout blk_layout(long long n, long long m, size_t off) {
+  BlkLayout L;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t N = (size_t)n, M = (size_t)m;
+  L.bstart = take(4 * (N + 1));
+  L.bmeta = take(16 * N);
+  L.verts = take(4 * N);
+  L.blk_of = take(4 * N);
+  L.irow = take(4 * (N + 1));
+  L.xrow = take(4 * (N + 1));
+  L.iedge = take(4 * M);
+  L.xcol = take(4 * M);
+  L.xw = take(4 * M);
+  L.xblk = take(4 * M);
+  L.brel = take(4 * N);
+  L.bstate = take(4 * N);
+  L.ring_cap = 1;
+  while (L.ring_cap < N + 1) L.ring_cap <<= 1;  // more slots than blocks
+  L.ring = take(8 * (size_t)L.ring_cap);
+  L.lab = take(8 * N);
+  L.fr = take(4 * N);
+  L.cnt = take(4 * N);
+  L.ecnt = take(4 * N);
+  L.far = take(8 * N);
+  L.over = take(4 * N);
+  L.flag = take(4 * (N + 1));
+  L.bsize = take(4 * (N + 1));
+  L.fill = take(4 * N);
+  L.pos = take(4 * N);
+  L.icnt = take(4 * (N + 1));
+  L.xcnt = take(4 * (N + 1));
+  L.tiles = take(4 * ((N + 1) / kScanTile + 2));
+  L.flags = take(256);
+  L.end = off;
+  return L;
+}
 
 int pull_mode(const og_schedule* r) {
   return (r->flags & OG_FLAG_DENSE_PULL) ? kPullAlways : (r->flags & OG_FLAG_HYBRID_DIRECTION) ? kPullHybrid : kPullNever;
@@ -2645,6 +3572,7 @@ size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   // bitmap) and the long rows' slices
   if (pull_mode(r) != kPullNever)
     b += (sh.core ? vec_bytes((nv + 31) / 32) : vec_bytes(2 * nv)) + vec_bytes(2 * (long long)slice_cap(g->m));
+  if (blocks_on(r, sh)) b = blk_layout(g->n, g->m, b).end;
   return b;
 }
 
@@ -2659,9 +3587,15 @@ bool schedule_ok(const og_schedule* s) {
     return false;
   if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
   if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL |
-                   OG_FLAG_HYBRID_DIRECTION | OG_FLAG_DEGREE_BINS | OG_FLAG_KEEP_SPLIT))
+                   OG_FLAG_HYBRID_DIRECTION | OG_FLAG_DEGREE_BINS | OG_FLAG_KEEP_SPLIT | OG_FLAG_VERTEX_BLOCKS |
+                   OG_FLAG_KEEP_BLOCKS))
     return false;
-  if (s->bin_thread < 0 || s->bin_wave < 0) return false;
+  if (s->bin_thread < 0 || s->bin_wave < 0 || s->block_size < 0) return false;
+  // the vertex-block engine: its own instantiation, always fused, persistent
+  if ((s->flags & OG_FLAG_VERTEX_BLOCKS) &&
+      ((s->flags & (OG_FLAG_LIGHT_HEAVY | OG_FLAG_DEGREE_BINS | OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION)) ||
+       s->update != OG_EAGER_WITH_FUSION || s->engine != OG_ENGINE_PERSISTENT))
+    return false;
   // degree bins are their own instantiation: not with the split or a pull direction
   if ((s->flags & OG_FLAG_DEGREE_BINS) &&
       (s->flags & (OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION)))
@@ -2707,13 +3641,23 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
 // round) chained in stream order.  Kept per host thread and reused while the
 // kernel, grid, device and arguments are unchanged (repeated queries on one
 // graph and workspace share them: the per-query sources live in the
-// workspace).  Never destroyed at exit: the runtime may be gone by then.
+// workspace).  Destroyed by og_release; never at exit, when the runtime may
+// be gone already.
 struct RoundGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void* func = nullptr;
   int nwg = 0, nodes = 0, dev = -1;
   Args args;
+  bool release() {
+    bool good = true;
+    if (exec && hipGraphExecDestroy(exec) != hipSuccess) good = false;
+    if (graph && hipGraphDestroy(graph) != hipSuccess) good = false;
+    exec = nullptr;
+    graph = nullptr;
+    func = nullptr;
+    return good;
+  }
 };
 thread_local RoundGraph t_round_graph;
 
@@ -2766,6 +3710,112 @@ hipGraphExec_t round_graph(const Args& a, int nwg, int group, int dev) {
   return ex;
 }
 
+// Exclusive prefix sum of cnt ints (in place allowed).
+void scan_excl(const int* in, int* out, long long cnt, int* tiles, int grid, hipStream_t st) {
+  const long long nt = (cnt + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kBlock), 0, st, in, out, cnt, tiles);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, st, tiles, (int)nt);
+  hipLaunchKernelGGL(k_scan_add, dim3(grid), dim3(kBlock), 0, st, out, cnt, (const int*)tiles);
+}
+
+bool read_back(void* host, const void* dev, size_t bytes, hipStream_t st) {
+  return hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess;
+}
+
+// Builds the blocked copy of g in the workspace (layout L at base): the
+// clustering passes, the block numbering, each block's vertices in id
+// order, and the internal / leaving edge lists.  Waits on the stream
+// between passes.  *nb_out receives the block count.
+og_status build_blocks(const og_graph* g, int target, char* base, const BlkLayout& L, int grid, hipStream_t st,
+                       int* nb_out) {
+  const int n = g->n;
+  const long long* rp = (const long long*)g->row_ptr;
+  const int* col = g->col;
+  const int* w = g->w;
+  auto at = [&](size_t off) { return (void*)(base + off); };
+  unsigned long long* lab = (unsigned long long*)at(L.lab);
+  unsigned long long* far = (unsigned long long*)at(L.far);
+  int* fr = (int*)at(L.fr);
+  int* cnt = (int*)at(L.cnt);
+  int* ecnt = (int*)at(L.ecnt);
+  int* over = (int*)at(L.over);
+  unsigned* flags = (unsigned*)at(L.flags);
+  int* tiles = (int*)at(L.tiles);
+  unsigned rate = (unsigned)(target > 0 ? target : 1);
+  constexpr int kLevels = 4;  // BFS levels launched between two checks
+  for (int pass = 0;; ++pass) {
+    if (pass >= 64) return OG_ERR_INTERNAL;
+    hipLaunchKernelGGL(k_cl_prep, dim3(grid), dim3(kBlock), 0, st, n, lab, fr, (const int*)over,
+                       (const unsigned long long*)far, (const int*)cnt, (const int*)ecnt, rate, target, pass,
+                       0x9e3779b9u * (unsigned)(pass + 1));
+    for (long long level = 0;; level += kLevels) {
+      if (level > (long long)n + kLevels) return OG_ERR_INTERNAL;
+      hipLaunchKernelGGL(k_fill, dim3(1), dim3(kWave), 0, st, (int*)flags, (long long)kLevels, 0);
+      for (int k = 0; k < kLevels; ++k)
+        hipLaunchKernelGGL(k_cl_bfs, dim3(grid), dim3(kBlock), 0, st, n, rp, col, lab, (const int*)fr,
+                           (unsigned)(level + k), flags + k);
+      unsigned hf[kLevels];
+      if (hipGetLastError() != hipSuccess || !read_back(hf, flags, sizeof(hf), st)) return OG_ERR_HIP;
+      if (hf[kLevels - 1] == 0) break;  // the frontier after the group's last level is empty
+    }
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, cnt, (long long)n, 0);
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, ecnt, (long long)n, 0);
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, (int*)far, 2LL * n, 0);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kWave), 0, st, (int*)flags, 2LL, 0);
+    hipLaunchKernelGGL(k_cl_count, dim3(grid), dim3(kBlock), 0, st, n, rp, col, w, (const unsigned long long*)lab,
+                       cnt, ecnt, far);
+    hipLaunchKernelGGL(k_cl_over, dim3(grid), dim3(kBlock), 0, st, n, (const unsigned long long*)lab,
+                       (const int*)cnt, (const int*)ecnt, over, flags);
+    unsigned hf[2];
+    if (hipGetLastError() != hipSuccess || !read_back(hf, flags, sizeof(hf), st)) return OG_ERR_HIP;
+    if (hf[0] == 0 && hf[1] == 0) break;  // no oversized cell, every vertex labelled
+    rate = rate > 8 ? rate / 8 : 1;
+  }
+  int* flag = (int*)at(L.flag);
+  int* bsize = (int*)at(L.bsize);
+  int* bstart = (int*)at(L.bstart);
+  int* verts = (int*)at(L.verts);
+  int* blk_of = (int*)at(L.blk_of);
+  int* fill = (int*)at(L.fill);
+  int* pos = (int*)at(L.pos);
+  int* icnt = (int*)at(L.icnt);
+  int* xcnt = (int*)at(L.xcnt);
+  int* irow = (int*)at(L.irow);
+  int* xrow = (int*)at(L.xrow);
+  // block ids: seeds in increasing id order
+  hipLaunchKernelGGL(k_cl_isseed, dim3(grid), dim3(kBlock), 0, st, n, (const unsigned long long*)lab, flag);
+  scan_excl(flag, flag, (long long)n + 1, tiles, grid, st);
+  int nb = 0;
+  if (hipGetLastError() != hipSuccess || !read_back(&nb, flag + n, sizeof(int), st)) return OG_ERR_HIP;
+  if (nb < 1 || nb > n) return OG_ERR_INTERNAL;
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, bsize, (long long)nb + 1, 0);
+  hipLaunchKernelGGL(k_cl_assign, dim3(grid), dim3(kBlock), 0, st, n, (const unsigned long long*)lab,
+                     (const int*)flag, blk_of, bsize);
+  scan_excl(bsize, bstart, (long long)nb + 1, tiles, grid, st);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(kBlock), 0, st, fill, (long long)nb, 0);
+  hipLaunchKernelGGL(k_cl_scatter, dim3(grid), dim3(kBlock), 0, st, n, (const int*)blk_of, (const int*)bstart, fill,
+                     verts);
+  hipLaunchKernelGGL(k_cl_sort, dim3(nb < 65536 ? nb : 65536), dim3(kBlock), 0, st, nb, (const int*)bstart, verts);
+  hipLaunchKernelGGL(k_cl_pos, dim3(grid), dim3(kBlock), 0, st, n, (const int*)verts, pos);
+  hipLaunchKernelGGL(k_cl_ecount, dim3(grid), dim3(kBlock), 0, st, n, rp, col, w, (const int*)verts,
+                     (const int*)blk_of, icnt, xcnt);
+  scan_excl(icnt, irow, (long long)n + 1, tiles, grid, st);
+  scan_excl(xcnt, xrow, (long long)n + 1, tiles, grid, st);
+  hipLaunchKernelGGL(k_cl_efill, dim3(grid), dim3(kBlock), 0, st, n, rp, col, w, (const int*)verts,
+                     (const int*)blk_of, (const int*)pos, (const int*)bstart, (const int*)irow, (const int*)xrow,
+                     (unsigned*)at(L.iedge), (int*)at(L.xcol), (int*)at(L.xw), (int*)at(L.xblk));
+  hipLaunchKernelGGL(k_cl_meta, dim3(grid), dim3(kBlock), 0, st, nb, (const int*)bstart, (const int*)irow,
+                     (int4*)at(L.bmeta));
+  int ends[2] = {0, 0};
+  if (hipGetLastError() != hipSuccess || !read_back(&ends[0], irow + n, sizeof(int), st) ||
+      !read_back(&ends[1], xrow + n, sizeof(int), st))
+    return OG_ERR_HIP;
+  if ((long long)ends[0] + ends[1] != g->m) return OG_ERR_INTERNAL;
+  *nb_out = nb;
+  return OG_OK;
+}
+
 // Common driver.  vsrcs: nsrc virtual source ids; vtgts: reps virtual
 // target ids or empty.  The caller has validated every argument.
 template <class W>
@@ -2779,6 +3829,9 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   og_schedule r = resolved(sched);
   if (force_delta1) r.delta = 1;
   if (ws_size < ws_bytes_for(g, &r, sh)) return fail(OG_ERR_WORKSPACE);
+  // the block engine shares the int32 engine's initialisation and
+  // predecessor kernels
+  using PW = typename std::conditional<W::kBlocks, IntW, W>::type;
 
   hipStream_t stream = (hipStream_t)stream_v;
   int dev = 0;
@@ -2794,6 +3847,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
                   : std::is_same<W, CorePullW>::value ? di.occ_core_pull
                   : std::is_same<W, BinW>::value      ? di.occ_bin
                   : std::is_same<W, BinFloatW>::value ? di.occ_bin_float
+                  : std::is_same<W, BlockW>::value    ? di.occ_blocks
                                                       : di.occ_int;
   int maxwg = di.cus * (occ > 0 ? occ : 1);
   int nwg = r.workgroups > 0 ? r.workgroups : maxwg;
@@ -2804,6 +3858,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   const long long cap = queue_cap(g, &r, sh);
   int *split_col = nullptr, *split_w = nullptr, *split_l = nullptr, *split_big = nullptr;
   int2* pull_slices = nullptr;
+  BlkLayout bl{};
   char* base = (char*)ws;
   int* table = (int*)(base + kCtlBytes);
   Args a;
@@ -2888,19 +3943,43 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       a.slices = pull_slices;
       off += vec_bytes(2 * (long long)slice_cap(g->m));
     }
+    if constexpr (W::kBlocks) {
+      bl = blk_layout(g->n, g->m, off);
+      a.bstart = (const int*)(base + bl.bstart);
+      a.bmeta = (const int4*)(base + bl.bmeta);
+      a.verts = (const int*)(base + bl.verts);
+      a.blk_of = (const int*)(base + bl.blk_of);
+      a.irow = (const int*)(base + bl.irow);
+      a.xrow = (const int*)(base + bl.xrow);
+      a.iedge = (const unsigned*)(base + bl.iedge);
+      a.xcol = (const int*)(base + bl.xcol);
+      a.xw = (const int*)(base + bl.xw);
+      a.xblk = (const int*)(base + bl.xblk);
+      a.brel = (int*)(base + bl.brel);
+      a.bstate = (unsigned*)(base + bl.bstate);
+      a.ring = (unsigned long long*)(base + bl.ring);
+      a.ring_mask = (unsigned)(bl.ring_cap - 1);
+    }
   }
 
   // Before anything is launched: this call's layout may cover a split copy
   // held in the workspace, unless it is the same copy, kept on request.
   SplitKey split_key{};
   bool keep_split = false;
+  long long kept_nb = 0;
   if constexpr (W::kSplit) {
-    split_key = SplitKey{ws, g->row_ptr, g->col, g->w, (long long)g->n, g->m, a.delta, split_col};
+    split_key = SplitKey{ws, g->row_ptr, g->col, g->w, (long long)g->n, g->m, a.delta, split_col, 0};
     keep_split = (r.flags & OG_FLAG_KEEP_SPLIT) && split_kept(split_key);
+  }
+  if constexpr (W::kBlocks) {
+    split_key = SplitKey{ws, g->row_ptr, g->col, g->w, (long long)g->n, g->m, (unsigned)r.block_size,
+                         base + bl.bstart, 1};
+    keep_split = (r.flags & OG_FLAG_KEEP_BLOCKS) && split_kept(split_key, &kept_nb);
   }
   if (!keep_split) forget_split(ws);
 
   const bool timing = (r.flags & OG_FLAG_TIMING) && !(r.flags & OG_FLAG_ASYNC) && t_timers.init();
+  float prep_ms = 0.f;
   if (timing) (void)hipEventRecord(t_timers.ev[0], stream);
   // query table: sources then targets, carried in kernel arguments
   {
@@ -2923,7 +4002,7 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   } else {
     hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int)W::kInfBits);
     hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
-    hipLaunchKernelGGL(k_init_sources<W>, dim3(src_grid), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL(k_init_sources<PW>, dim3(src_grid), dim3(kBlock), 0, stream, a);
   }
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);
   if constexpr (W::kPull) {
@@ -2969,14 +4048,39 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       record_split(split_key);
     }
   }
+  if constexpr (W::kBlocks) {
+    // the blocked copy (built here unless kept), then the per-query block
+    // state: no vertex relaxed yet, every block clean, an empty ring
+    if (!keep_split) {
+      if (timing) (void)hipEventRecord(t_timers.ev[4], stream);
+      int nbb = 0;
+      const og_status bs = build_blocks(g, r.block_size, base, bl, fill_grid, stream, &nbb);
+      if (bs != OG_OK) return fail(bs);
+      if (timing) {
+        (void)hipEventRecord(t_timers.ev[5], stream);
+        if (hipEventSynchronize(t_timers.ev[5]) != hipSuccess ||
+            hipEventElapsedTime(&prep_ms, t_timers.ev[4], t_timers.ev[5]) != hipSuccess)
+          prep_ms = 0.f;
+      }
+      kept_nb = nbb;
+      split_key.nb = nbb;
+      record_split(split_key);
+    }
+    a.nb = (int)kept_nb;
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, a.brel, (long long)g->n, kInf);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, (int*)a.bstate, kept_nb, 0);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kBlock), 0, stream, (int*)a.ring, 2 * (long long)bl.ring_cap, 0);
+  }
   if (timing) (void)hipEventRecord(t_timers.ev[1], stream);
 
   if (persistent) {
     void* kargs[] = {&a};
-    if (hipLaunchCooperativeKernel((const void*)k_persistent<W>, dim3(nwg), dim3(kBlock), kargs, 0, stream) !=
-        hipSuccess)
+    const void* kern;
+    if constexpr (W::kBlocks) kern = (const void*)k_blocks<W>;
+    else kern = (const void*)k_persistent<W>;
+    if (hipLaunchCooperativeKernel(kern, dim3(nwg), dim3(kBlock), kargs, 0, stream) != hipSuccess)
       return fail(OG_ERR_HIP);
-  } else {
+  } else if constexpr (!W::kBlocks) {
     // Launch rounds in groups and poll the done flag between groups; a
     // launch after completion returns at once.  OG_ENGINE_GRAPH_ROUNDS
     // replays one executable hipGraph holding the group's launches.
@@ -3033,22 +4137,22 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
       }
     }
     if (sum) {
-      hipLaunchKernelGGL((k_pred_edges<W, true>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+      hipLaunchKernelGGL((k_pred_edges<PW, true>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
                          (const unsigned long long*)sum);
-      hipLaunchKernelGGL((k_pred_long<W, true>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+      hipLaunchKernelGGL((k_pred_long<PW, true>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
                          (const unsigned long long*)sum);
     } else {
-      hipLaunchKernelGGL((k_pred_edges<W, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+      hipLaunchKernelGGL((k_pred_edges<PW, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
                          (const unsigned long long*)nullptr);
       if (longs)
-        hipLaunchKernelGGL((k_pred_long<W, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
+        hipLaunchKernelGGL((k_pred_long<PW, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, longs, lcap,
                            (const unsigned long long*)nullptr);
     }
     hipLaunchKernelGGL(k_pred_fix, dim3(fill_grid), dim3(kBlock), 0, stream, pred, (long long)a.n);
     hipLaunchKernelGGL(k_pred_sources, dim3(src_grid), dim3(kBlock), 0, stream, a, pred);
     if (pred_edge) hipLaunchKernelGGL(k_pred_edge_ids, dim3(fill_grid), dim3(kBlock), 0, stream, a, pred, pred_edge);
   } else if (stats) {
-    hipLaunchKernelGGL((k_pred_edges<W, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr,
+    hipLaunchKernelGGL((k_pred_edges<PW, false>), dim3(fill_grid), dim3(kBlock), 0, stream, a, (int*)nullptr,
                        (int2*)nullptr, 0ull, (const unsigned long long*)nullptr);
   }
   if (timing) (void)hipEventRecord(t_timers.ev[3], stream);
@@ -3062,6 +4166,10 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     return fail(OG_ERR_HIP);
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(OG_ERR_HIP);
   fill_stats(hc, stats, nwg);
+  if (stats && W::kBlocks) {
+    stats->blocks = kept_nb;
+    stats->prep_ms = prep_ms;
+  }
   if (timing && stats) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t_timers.ev[0], t_timers.ev[1]) == hipSuccess) stats->init_ms = ms;
@@ -3101,6 +4209,15 @@ og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, cons
     }
   }
   if (pred_edge && !pred) return fail(OG_ERR_INVALID_ARG);
+  if (s->flags & OG_FLAG_VERTEX_BLOCKS) {
+    // one query at a time, no A* estimate (the blocks drain buckets of plain
+    // distances)
+    if constexpr (std::is_same<W, IntW>::value) {
+      if (reps == 1 && !h)
+        return run<BlockW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
+    }
+    return fail(OG_ERR_INVALID_ARG);
+  }
   if (s->flags & OG_FLAG_LIGHT_HEAVY) {
     if constexpr (std::is_same<W, IntW>::value)
       return run<SplitW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
@@ -3150,6 +4267,7 @@ og_status og_default_schedule(og_schedule* s) {
   s->engine = OG_ENGINE_PERSISTENT;
   s->bin_thread = og::kBinLane;
   s->bin_wave = og::kDefaultBinWave;
+  s->block_size = og::kDefaultBlockSize;
   return OG_OK;
 }
 
@@ -3283,7 +4401,7 @@ size_t og_workspace_bytes_kcore(const og_graph* g, const og_schedule* s) {
   if (!s) return 0;
   og_schedule r = og::resolved(s);
   r.delta = 1;
-  r.flags &= ~(OG_FLAG_LIGHT_HEAVY | OG_FLAG_DEGREE_BINS);
+  r.flags &= ~(OG_FLAG_LIGHT_HEAVY | OG_FLAG_DEGREE_BINS | OG_FLAG_VERTEX_BLOCKS | OG_FLAG_KEEP_BLOCKS);
   if (!og::graph_ok(g, false) || !og::schedule_ok(&r)) return 0;
   return og::ws_bytes_for(g, &r, og::Shape{1, g->n, false, true});
 }
@@ -3298,7 +4416,7 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
   if (!s) return fail(OG_ERR_INVALID_ARG);
   og_schedule r = *s;
   r.delta = 1;  // one bucket per degree value: peeling needs the strict order
-  r.flags &= ~(OG_FLAG_LIGHT_HEAVY | OG_FLAG_DEGREE_BINS);
+  r.flags &= ~(OG_FLAG_LIGHT_HEAVY | OG_FLAG_DEGREE_BINS | OG_FLAG_VERTEX_BLOCKS | OG_FLAG_KEEP_BLOCKS);
   if (!og::graph_ok(g, false) || !og::schedule_ok(&r) || !core || !ws) return fail(OG_ERR_INVALID_ARG);
   if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
   const og::Shape sh{1, g->n, false, true};
@@ -3307,6 +4425,15 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
     return og::run<og::CorePullW>(g, sh, {}, {}, nullptr, &r, core, nullptr, nullptr, ws, ws_bytes, stats, stream,
                                   false);
   return og::run<og::CoreW>(g, sh, {}, {}, nullptr, &r, core, nullptr, nullptr, ws, ws_bytes, stats, stream, false);
+}
+
+og_status og_release(void) {
+  // outstanding work on the calling thread's streams may still use the
+  // round graph: wait for the device first
+  bool good = hipDeviceSynchronize() == hipSuccess;
+  good = og::t_round_graph.release() && good;
+  good = og::t_timers.release() && good;
+  return good ? OG_OK : OG_ERR_HIP;
 }
 
 og_status og_read_stats(const void* ws, og_stats* stats, void* stream) {

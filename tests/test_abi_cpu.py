@@ -56,7 +56,7 @@ def test_default_schedule():
     s = _lib.OgSchedule()
     assert lib.og_default_schedule(ctypes.byref(s)) == 0
     assert s.delta == 1 and s.update == 1 and s.window_buckets == 16 and s.fusion_threshold == 1024
-    assert s.bin_thread == 4 and s.bin_wave == 64
+    assert s.bin_thread == 4 and s.bin_wave == 64 and s.block_size == 2048
     assert lib.og_default_schedule(None) == og.OG_ERR_INVALID_ARG
 
 
@@ -112,11 +112,13 @@ def test_workspace_bytes():
 
 @pytest.mark.parametrize("field,value", [
     ("delta", 0), ("update", 3), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
-    ("max_rounds", -1), ("flags", 256), ("fusion_threshold", -2),
+    ("max_rounds", -1), ("flags", 1024), ("fusion_threshold", -2),
     # a pull direction needs lazy updates, and takes one direction flag
     ("flags", 16), ("flags", 32),
     # degree bins: non-negative cut-offs, not with the split or a pull direction
     ("bin_thread", -1), ("bin_wave", -1), ("flags", 64 | 8), ("flags", 64 | 16),
+    # vertex blocks: not with the split, the degree bins or a pull direction; a non-negative block size
+    ("flags", 256 | 8), ("flags", 256 | 64), ("flags", 256 | 16), ("block_size", -1),
 ])
 def test_invalid_schedule_rejected(field, value):
     lib = _lib.load()
@@ -217,3 +219,63 @@ def test_binding_argument_checks_survive_optimisation():
     src = open(os.path.join(ROOT, "paper_1911_07260_amd", "__init__.py")).read()
     src += open(os.path.join(ROOT, "paper_1911_07260_amd", "diff.py")).read()
     assert not re.search(r"^\s*assert\b", src, flags=re.M)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(update=og.OG_EAGER_NO_FUSION), dict(update=og.OG_LAZY_UPDATE),
+    dict(engine=og.OG_ENGINE_HOST_ROUNDS), dict(engine=og.OG_ENGINE_GRAPH_ROUNDS),
+])
+def test_vertex_blocks_need_fused_persistent(kw):
+    """The vertex-block engine is bucket fusion in a persistent launch: any
+    other update or engine is rejected before anything is launched."""
+    lib = _lib.load()
+    g = _fake_graph()
+    sc = og.Schedule(delta=4, flags=og.OG_FLAG_VERTEX_BLOCKS, **kw).to_c()
+    st = _lib.OgStats()
+    rc = lib.og_sssp(ctypes.byref(g), 0, ctypes.byref(sc), ctypes.c_void_p(0x4000), None,
+                     ctypes.c_void_p(0x10000), ctypes.c_size_t(1 << 40), ctypes.byref(st), None)
+    assert rc == og.OG_ERR_INVALID_ARG
+
+
+def test_vertex_blocks_single_query_only():
+    """Batches and A* estimates are rejected with the block engine."""
+    import numpy as np
+    lib = _lib.load()
+    g = _fake_graph()
+    sc = og.Schedule(delta=4, flags=og.OG_FLAG_VERTEX_BLOCKS).to_c()
+    st = _lib.OgStats()
+    srcs = np.array([0, 1], dtype=np.int32)
+    rc = lib.og_sssp_batch(ctypes.byref(g), ctypes.c_void_p(srcs.ctypes.data), 2, ctypes.byref(sc),
+                           ctypes.c_void_p(0x4000), None, ctypes.c_void_p(0x10000), ctypes.c_size_t(1 << 40),
+                           ctypes.byref(st), None)
+    assert rc == og.OG_ERR_INVALID_ARG
+    rc = lib.og_astar(ctypes.byref(g), 0, 1, ctypes.c_void_p(0x8000), ctypes.byref(sc), ctypes.c_void_p(0x4000),
+                      None, ctypes.c_void_p(0x10000), ctypes.c_size_t(1 << 40), ctypes.byref(st), None)
+    assert rc == og.OG_ERR_INVALID_ARG
+
+
+def test_vertex_blocks_workspace_bytes():
+    """The block engine's workspace: the plain layout, then the blocked copy
+    (block starts, per-block offsets and sizes, vertices in block order,
+    block of each vertex, internal
+    and leaving row offsets, internal edges, leaving edges' targets, weights
+    and target blocks), the per-query state (processed labels, block states,
+    a ring of a power of two above n entries) and the build's temporaries."""
+    lib = _lib.load()
+    for n, m in ((1000, 4000), (4096, 16128), (5000, 100_000)):
+        g = _fake_graph(n, m)
+        plain = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000).to_c()
+        blk = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, flags=og.OG_FLAG_VERTEX_BLOCKS).to_c()
+        base = lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(plain))
+
+        def v(nbytes):
+            return (nbytes + 255) // 256 * 256
+
+        ring = 1
+        while ring < n + 1:
+            ring *= 2
+        copy = v(4 * (n + 1)) + v(16 * n) + 2 * v(4 * n) + 2 * v(4 * (n + 1)) + 4 * v(4 * m)
+        query = 2 * v(4 * n) + v(8 * ring)
+        build = (v(8 * n) + 3 * v(4 * n) + v(8 * n) + v(4 * n) + 2 * v(4 * (n + 1)) + 2 * v(4 * n)
+                 + 2 * v(4 * (n + 1)) + v(4 * ((n + 1) // 2048 + 2)) + 256)
+        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(blk)) == base + copy + query + build
