@@ -397,6 +397,25 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
  * stream has been synchronised.  Blocking copy on stream. */
 og_status og_read_stats(const void* ws, og_stats* stats, void* stream);
 
+/* ---- A call that allocates nothing -------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * og_sssp_noalloc is og_sssp with the workspace taken from a fixed device
+ * array inside the library, OG_SCRATCH_BYTES (32 MiB) per device, present
+ * from the library's load on that device until the process ends.  The
+ * caller still owns dist and pred.  It calls no hipMalloc / hipFree and
+ * creates no HIP object, so OG_FLAG_TIMING and OG_ENGINE_GRAPH_ROUNDS are
+ * rejected (OG_ERR_INVALID_ARG); a graph and schedule whose
+ * og_workspace_bytes() exceed OG_SCRATCH_BYTES return OG_ERR_WORKSPACE
+ * with nothing launched (a smaller schedule.queue_capacity shrinks the
+ * need).  Every call on one device uses the same array and leaves its
+ * contents behind (each call initialises what it reads): calls that
+ * overlap in time on one device race and must not be made.  Results are
+ * those of og_sssp. */
+#define OG_SCRATCH_BYTES ((size_t)32 << 20)
+og_status og_sssp_noalloc(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
+                          og_stats* stats, void* stream);
+
 /* Releases what the library keeps per host thread between calls: the HIP
  * events of OG_FLAG_TIMING and the executable round graph of
  * OG_ENGINE_GRAPH_ROUNDS (both are recreated on demand by a later call).

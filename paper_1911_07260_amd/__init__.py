@@ -38,6 +38,7 @@ from ._lib import (OG_EAGER_NO_FUSION, OG_EAGER_WITH_FUSION, OG_ENGINE_GRAPH_ROU
                    OG_ERR_OVERFLOW, OG_ERR_ROUND_LIMIT, OG_ERR_WORKSPACE, OG_FLAG_ASYNC, OG_FLAG_DEGREE_BINS,
                    OG_FLAG_DENSE_PULL, OG_FLAG_HYBRID_DIRECTION, OG_FLAG_KEEP_BLOCKS, OG_FLAG_KEEP_SPLIT,
                    OG_FLAG_LIGHT_HEAVY, OG_FLAG_TIMING, OG_FLAG_VALIDATE, OG_FLAG_VERTEX_BLOCKS, OG_LAZY_UPDATE, OG_OK,
+                   OG_SCRATCH_BYTES,
                    OgError, OgGraph, OgSchedule, OgStats)
 
 INF = 2**31 - 1
@@ -50,7 +51,7 @@ def _require(ok: bool, what: str) -> None:
         raise ValueError(what)
 
 __all__ = [
-    "DeviceGraph", "Schedule", "Workspace", "sssp", "wbfs", "ppsp", "astar", "sssp_batch", "ppsp_batch",
+    "DeviceGraph", "Schedule", "Workspace", "sssp", "sssp_noalloc", "wbfs", "ppsp", "astar", "sssp_batch", "ppsp_batch",
     "astar_batch", "sssp_multi", "kcore", "workspace_bytes", "status_string", "version", "release", "INF",
     "OgError",
 ]
@@ -207,6 +208,36 @@ def sssp(graph: DeviceGraph, src: int, schedule: Schedule | None = None, pred: b
          ws: Workspace | None = None, stream=None, **kw):
     """Single-source shortest paths (og_sssp)."""
     return _call("og_sssp", graph, [int(src)], schedule, pred, ws, stream, **kw)
+
+
+def sssp_noalloc(graph: DeviceGraph, src: int, schedule: Schedule | None = None, pred: bool = True,
+                 stream=None, out_dist: torch.Tensor | None = None, out_pred: torch.Tensor | None = None,
+                 check: bool = True):
+    """og_sssp_noalloc: og_sssp on the library's fixed per-device workspace
+    (OG_SCRATCH_BYTES); no device allocation by the library.  Calls that
+    overlap on one device must not be made."""
+    lib = _lib.load()
+    schedule = schedule or Schedule()
+    dev = graph.device
+    dist = out_dist if out_dist is not None else torch.empty(graph.n, dtype=torch.int32, device=dev)
+    pr = out_pred if out_pred is not None else (torch.empty(graph.n, dtype=torch.int32, device=dev) if pred else None)
+    _require(dist.numel() == graph.n and dist.dtype == torch.int32 and dist.is_contiguous(),
+             f"output dist must be a contiguous int32 tensor of {graph.n} entries")
+    _require(pr is None or (pr.numel() == graph.n and pr.dtype == torch.int32 and pr.is_contiguous()),
+             f"output pred must be a contiguous int32 tensor of {graph.n} entries")
+    g = graph.to_c()
+    s = schedule.to_c()
+    st = OgStats()
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    status = lib.og_sssp_noalloc(ctypes.byref(g), int(src), ctypes.byref(s), ctypes.c_void_p(dist.data_ptr()),
+                                 ctypes.c_void_p(pr.data_ptr()) if pr is not None else None, ctypes.byref(st),
+                                 ctypes.c_void_p(stream.cuda_stream))
+    stats = st.as_dict()
+    stats["status"] = int(status)
+    if check and status != OG_OK:
+        raise OgError(status, "og_sssp_noalloc", lib)
+    return dist, pr, stats
 
 
 def wbfs(graph: DeviceGraph, src: int, schedule: Schedule | None = None, pred: bool = True,

@@ -32,6 +32,8 @@ OG_FLAG_KEEP_SPLIT = 128
 OG_FLAG_VERTEX_BLOCKS = 256
 OG_FLAG_KEEP_BLOCKS = 512
 
+OG_SCRATCH_BYTES = 32 << 20  # og_sssp_noalloc's fixed workspace per device
+
 OG_EAGER_NO_FUSION = 0
 OG_EAGER_WITH_FUSION = 1
 OG_LAZY_UPDATE = 2
@@ -171,6 +173,8 @@ def load():
     lib.og_workspace_bytes_kcore.argtypes = [P(OgGraph), P(OgSchedule)]
     lib.og_kcore.restype = i32
     lib.og_kcore.argtypes = [P(OgGraph), P(OgSchedule), vp, vp, ctypes.c_size_t, P(OgStats), vp]
+    lib.og_sssp_noalloc.restype = i32
+    lib.og_sssp_noalloc.argtypes = [P(OgGraph), i32, P(OgSchedule), vp, vp, P(OgStats), vp]
     lib.og_release.restype = i32
     lib.og_release.argtypes = []
     lib.og_read_stats.restype = i32

@@ -4427,6 +4427,58 @@ og_status og_kcore(const og_graph* g, const og_schedule* s, int32_t* core, void*
   return og::run<og::CoreW>(g, sh, {}, {}, nullptr, &r, core, nullptr, nullptr, ws, ws_bytes, stats, stream, false);
 }
 
+}  // extern "C"
+
+namespace og {
+
+// Workspace of og_sssp_noalloc: one copy per device, allocated with the code
+// object when the library is loaded on that device and held until the
+// process ends.  Host code never uses this name as an address: the device
+// address comes from hipGetSymbolAddress, per device.
+constexpr size_t kScratchBytes = OG_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64];
+
+// The device address of the current device's copy of scratch, looked up on
+// the first call on that device.
+og_status scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return OG_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OG_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return OG_OK;
+}
+
+}  // namespace og
+
+extern "C" {
+
+og_status og_sssp_noalloc(const og_graph* g, int32_t src, const og_schedule* s, int32_t* dist, int32_t* pred,
+                          og_stats* stats, void* stream) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  auto fail = [&](og_status st) {
+    if (stats) stats->status = st;
+    return st;
+  };
+  // timing events and the replayed round graph are HIP objects created on
+  // first use: not available here
+  if (!s || (s->flags & OG_FLAG_TIMING) || s->engine == OG_ENGINE_GRAPH_ROUNDS) return fail(OG_ERR_INVALID_ARG);
+  const size_t need = og_workspace_bytes(g, s);
+  if (need == 0) return fail(OG_ERR_INVALID_ARG);
+  if (need > og::kScratchBytes) return fail(OG_ERR_WORKSPACE);
+  void* ws = nullptr;
+  const og_status st = og::scratch_address(&ws);
+  if (st != OG_OK) return fail(st);
+  return og_sssp(g, src, s, dist, pred, ws, og::kScratchBytes, stats, stream);
+}
+
 og_status og_release(void) {
   // outstanding work on the calling thread's streams may still use the
   // round graph: wait for the device first

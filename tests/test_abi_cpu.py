@@ -279,3 +279,24 @@ def test_vertex_blocks_workspace_bytes():
         build = (v(8 * n) + 3 * v(4 * n) + v(8 * n) + v(4 * n) + 2 * v(4 * (n + 1)) + 2 * v(4 * n)
                  + 2 * v(4 * (n + 1)) + v(4 * ((n + 1) // 2048 + 2)) + 256)
         assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(blk)) == base + copy + query + build
+
+
+def test_noalloc_refusals_need_no_gpu():
+    """og_sssp_noalloc refuses, before touching the device, a schedule that
+    would create HIP objects and a graph whose workspace exceeds its fixed
+    array."""
+    lib = _lib.load()
+    st = _lib.OgStats()
+    small = _fake_graph(100, 400)
+    for sc in (og.Schedule(delta=4, flags=og.OG_FLAG_TIMING), og.Schedule(delta=4, engine=og.OG_ENGINE_GRAPH_ROUNDS),
+               og.Schedule(delta=0)):
+        c = sc.to_c()
+        rc = lib.og_sssp_noalloc(ctypes.byref(small), 0, ctypes.byref(c), ctypes.c_void_p(0x4000), None,
+                                 ctypes.byref(st), None)
+        assert rc == og.OG_ERR_INVALID_ARG and st.status == rc
+    big = _fake_graph(4_000_000, 16_000_000)
+    c = og.Schedule(delta=4).to_c()
+    assert lib.og_workspace_bytes(ctypes.byref(big), ctypes.byref(c)) > og.OG_SCRATCH_BYTES
+    rc = lib.og_sssp_noalloc(ctypes.byref(big), 0, ctypes.byref(c), ctypes.c_void_p(0x4000), None,
+                             ctypes.byref(st), None)
+    assert rc == og.OG_ERR_WORKSPACE and st.status == rc
