@@ -37,6 +37,7 @@ if ROOT not in sys.path:
 METRIC = "GTEPS + %HBM roofline, SSSP road-like 16.8M-V grid; fused vs unfused, batched vs serial"
 HBM_PEAK_GBS = 8000.0
 SWEEP = (256, 512, 1024, 2048, 4096, 8192, 16384)  # the configuration's Delta range, 2^8..2^14
+BATCH_SIZES = (64, 128, 256)  # queries per og_sssp_batch call in the batched legs
 # the paper's multicore-CPU figures for this path (context, not a target):
 # a 24-core / 48-thread dual-socket Xeon E5-2695 v3 with 128 GB DDR3-1600
 PAPER_CONTEXT = {
@@ -609,6 +610,14 @@ def main() -> int:
                 ("unfused_graph_rounds", og.OG_EAGER_NO_FUSION, og.OG_ENGINE_GRAPH_ROUNDS, TB),
                 ("lazy", og.OG_LAZY_UPDATE, og.OG_ENGINE_PERSISTENT, TB)):
             leg(name, og.Schedule(delta=d, update=upd, engine=eng, flags=fl))
+        # LDS-resident vertex blocks (bucket fusion inside blocks of about
+        # 1,024 vertices), the blocked copy built by the warm-up call and kept
+        blk = og.Schedule(delta=2048, flags=og.OG_FLAG_TIMING | og.OG_FLAG_VERTEX_BLOCKS | og.OG_FLAG_KEEP_BLOCKS,
+                          block_size=1024)
+        _, _, bst0 = og.sssp(dg, srcs[0], blk, ws=ws, out_dist=dist, out_pred=pred)
+        leg("vertex_blocks_d2048", blk)
+        variants["vertex_blocks_d2048"]["build_ms"] = round(bst0["prep_ms"], 3)
+        variants["vertex_blocks_d2048"]["blocks"] = bst0["blocks"]
         variants["sources"] = f"every variant: the {len(srcs)} headline sources (seed 1), one query each"
         variants["fused_vs_unfused_speedup"] = round(
             variants["unfused"]["engine_ms"] / variants["fused"]["engine_ms"], 2)
@@ -617,30 +626,47 @@ def main() -> int:
         variants["eager_fused_vs_lazy_speedup"] = round(
             variants["lazy"]["engine_ms"] / variants["fused"]["engine_ms"], 2)
         # batched: nq queries (the headline's sources first, then fresh ones
-        # from the same stream) in one persistent launch, against the same nq
-        # queries one per launch, with the same load balancing on both sides
+        # from the same stream) in one og_sssp_batch call, against the same
+        # queries one per launch, with the same load balancing on both sides.
+        # A call holds up to 127 road queries per launch (int32 virtual
+        # ids); 256 run as launches of 127, 127 and 2.
         nq = args.batch
-        bsrcs = [int(s) for s in gg.pick_sources(g, nq, seed=1)]
+        bsrcs_all = [int(s) for s in gg.pick_sources(g, max(BATCH_SIZES), seed=1)]
+        bsrcs = bsrcs_all[:nq]
         bws = og.Workspace(dev)
-        for lb_name, fl in (("flat", FLAT), ("degree_bins", TB)):
+
+        def batch_leg(name, srcs_b, fl):
+            per = min(len(srcs_b), (2**31 - 2) // g.n)
             bsched = og.Schedule(delta=d, update=og.OG_EAGER_WITH_FUSION, flags=fl,
-                                 queue_capacity=max(1 << 22, nq * (1 << 21)))
-            og.sssp_batch(dg, bsrcs, bsched, ws=bws)  # warm-up
+                                 queue_capacity=max(1 << 22, per * (1 << 21)))
+            og.sssp_batch(dg, srcs_b[:per], bsched, ws=bws, pred=False)  # warm-up
             torch.cuda.synchronize()
             t = time.perf_counter()
-            bd, bp, bst = og.sssp_batch(dg, bsrcs, bsched, ws=bws)
+            bd, bp, bst = og.sssp_batch(dg, srcs_b, bsched, ws=bws)
             torch.cuda.synchronize()
             bms = (time.perf_counter() - t) * 1e3
             del bd, bp
-            ser = leg(f"serial_{lb_name}", og.Schedule(delta=d, update=og.OG_EAGER_WITH_FUSION, flags=fl), bsrcs)
-            variants[f"batched_{lb_name}"] = {
-                "queries": nq, "ms_total": round(bms, 3), "ms_per_query": round(bms / nq, 3),
+            torch.cuda.empty_cache()
+            balg = 12.0 * bst["reached_edges"] + 28.0 * bst["reached_vertices"]
+            variants[name] = {
+                "queries": len(srcs_b), "queries_per_launch": per, "ms_total": round(bms, 3),
+                "ms_per_query": round(bms / len(srcs_b), 3),
                 "gteps": round(bst["reached_edges"] / (bms * 1e-3) / 1e9, 4), "engine_ms": round(bst["engine_ms"], 3),
-                "rounds": bst["rounds"], "vs_serial": round(ser["ms_per_query"] / (bms / nq), 2)}
-            print(f"[bench] batched {nq} queries ({lb_name}): {bms:.1f} ms ({bms / nq:.2f} ms/query)",
-                  file=sys.stderr, flush=True)
+                "rounds": bst["rounds"],
+                "alg_roofline_frac": round(balg / (bst["engine_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+            print(f"[bench] {name}: {bms:.1f} ms ({bms / len(srcs_b):.2f} ms/query)", file=sys.stderr, flush=True)
+            return variants[name]
+
+        for lb_name, fl in (("flat", FLAT), ("degree_bins", TB)):
+            b = batch_leg(f"batched_{lb_name}", bsrcs, fl)
+            ser = leg(f"serial_{lb_name}", og.Schedule(delta=d, update=og.OG_EAGER_WITH_FUSION, flags=fl), bsrcs)
+            b["vs_serial"] = round(ser["ms_per_query"] / b["ms_per_query"], 2)
+        for nb in BATCH_SIZES:
+            if nb != nq:
+                batch_leg(f"batched_flat_{nb}", bsrcs_all[:nb], FLAT)
         variants["batched_sources"] = (f"batched and serial legs: the same {nq} sources (seed 1; the first "
-                                       f"{len(srcs)} are the headline's), same load balancing on both sides")
+                                       f"{len(srcs)} are the headline's), same load balancing on both sides; "
+                                       f"batched_flat_<k>: the first k of the same stream")
         variants["batched_vs_serial"] = max(variants["batched_flat"]["vs_serial"],
                                             variants["batched_degree_bins"]["vs_serial"])
         del bws

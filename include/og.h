@@ -307,10 +307,15 @@ og_status og_astar(const og_graph* g, int32_t src, int32_t dst, const int32_t* h
 /* ---- Several queries in one launch ------------------------------------
  * Query q works on its own copy of the graph (virtual vertex q * n + v);
  * all queries share one bucket sequence, so a single persistent launch
- * serves the whole batch.  Requires nq * n < 2^31 and nq <= 1024.  srcs and
- * dsts are HOST arrays of nq base vertex ids; dist and pred are DEVICE arrays
- * of nq * n entries, query q's results at [q * n, (q + 1) * n) (pred holds
- * base vertex ids).  The workspace must hold og_workspace_bytes_batch(). */
+ * serves the whole batch.  One launch holds up to Q = min(1024,
+ * (2^31 - 2) / n) queries (virtual ids are int32); a batch of more (up to
+ * 2^20 queries) runs as consecutive launches of up to Q queries on the same
+ * workspace, each on its own slice of dist, pred and h, with the counters
+ * summed (not with OG_FLAG_ASYNC or OG_FLAG_VERTEX_BLOCKS:
+ * OG_ERR_INVALID_ARG).  srcs and dsts are HOST arrays of nq base vertex ids;
+ * dist and pred are DEVICE arrays of nq * n entries, query q's results at
+ * [q * n, (q + 1) * n) (pred holds base vertex ids).  The workspace must
+ * hold og_workspace_bytes_batch(), sized for min(nq, Q) queries. */
 size_t og_workspace_bytes_batch(const og_graph* g, const og_schedule* s, int32_t nq);
 
 /* nq independent single-source queries (og_sssp semantics per query). */

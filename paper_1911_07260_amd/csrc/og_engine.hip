@@ -80,7 +80,8 @@ constexpr int kGroup = 16;  // workgroups per first-level barrier counter
 constexpr int kMaxWg = 4096;
 constexpr int kMaxGroups = kMaxWg / kGroup;
 constexpr int kFlags = 64;  // release flags, one per 128-byte line
-constexpr int kMaxQueries = 1024;
+constexpr int kMaxQueries = 1024;    // queries in one launch
+constexpr int kMaxBatch = 1 << 20;  // queries in one batch call (in launches of at most kMaxQueries)
 constexpr size_t kCtlBytes = 65536;
 constexpr unsigned kNoBucket = 0xffffffffu;
 constexpr int kInf = INT_MAX;
@@ -4179,41 +4180,20 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   return (og_status)hc.status.v;
 }
 
-// Argument checks shared by every entry point (nothing is launched on
-// failure).  srcs / dsts are host arrays of base vertex ids.
-template <class W = IntW>
-og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, const int32_t* dsts, int32_t reps,
-                      bool multi, const int32_t* h, bool need_h, const og_schedule* s, int32_t* dist, int32_t* pred,
-                      void* ws, size_t ws_bytes, og_stats* stats, void* stream, bool force_delta1,
-                      int32_t* pred_edge = nullptr) {
-  if (stats) std::memset(stats, 0, sizeof(*stats));
+// The engine instantiation for a schedule and the call's weight type.
+template <class W>
+og_status dispatch(const og_graph* g, const Shape& sh, const std::vector<int>& vs, const std::vector<int>& vt,
+                   const int32_t* h, const og_schedule* s, int32_t* dist, int32_t* pred, int32_t* pred_edge,
+                   void* ws, size_t ws_bytes, og_stats* stats, void* stream, bool force_delta1) {
   auto fail = [&](og_status st) {
     if (stats) stats->status = st;
     return st;
   };
-  if (!graph_ok(g) || !schedule_ok(s) || !dist || !ws || !srcs) return fail(OG_ERR_INVALID_ARG);
-  if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
-  if (need_h && !h) return fail(OG_ERR_INVALID_ARG);
-  const Shape sh{reps, nsrc, dsts != nullptr};
-  if (!shape_ok(g, sh)) return fail(OG_ERR_INVALID_ARG);
-  std::vector<int> vs((size_t)nsrc), vt;
-  for (int i = 0; i < nsrc; ++i) {
-    if (srcs[i] < 0 || srcs[i] >= g->n) return fail(OG_ERR_INVALID_ARG);
-    vs[i] = multi ? srcs[i] : i * g->n + srcs[i];
-  }
-  if (dsts) {
-    vt.resize((size_t)reps);
-    for (int q = 0; q < reps; ++q) {
-      if (dsts[q] < 0 || dsts[q] >= g->n) return fail(OG_ERR_INVALID_ARG);
-      vt[q] = q * g->n + dsts[q];
-    }
-  }
-  if (pred_edge && !pred) return fail(OG_ERR_INVALID_ARG);
   if (s->flags & OG_FLAG_VERTEX_BLOCKS) {
     // one query at a time, no A* estimate (the blocks drain buckets of plain
     // distances)
     if constexpr (std::is_same<W, IntW>::value) {
-      if (reps == 1 && !h)
+      if (sh.reps == 1 && !h)
         return run<BlockW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
     }
     return fail(OG_ERR_INVALID_ARG);
@@ -4235,6 +4215,101 @@ og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, cons
       return run<BinFloatW>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
   }
   return run<W>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
+}
+
+// Queries one launch can hold on a graph of n vertices: virtual vertex ids
+// q * n + v are int32, and the target table of a launch has kMaxQueries
+// entries.
+int wave_queries(long long n) {
+  const long long q = (0x7fffffffLL - 1) / n;
+  return (int)(q < kMaxQueries ? q : kMaxQueries);
+}
+
+// Adds one wave's counters to a batch's (times and counts summed, the
+// largest queue fill, the first error).
+void add_stats(og_stats* to, const og_stats& w) {
+  if (to->status == OG_OK) to->status = w.status;
+  to->workgroups = w.workgroups;
+  to->rounds += w.rounds;
+  to->buckets += w.buckets;
+  to->relaxations += w.relaxations;
+  to->improvements += w.improvements;
+  to->pushes_local += w.pushes_local;
+  to->pushes_global += w.pushes_global;
+  to->far_pushes += w.far_pushes;
+  to->reached_vertices += w.reached_vertices;
+  to->reached_edges += w.reached_edges;
+  to->queue_needed = w.queue_needed > to->queue_needed ? w.queue_needed : to->queue_needed;
+  to->init_ms += w.init_ms;
+  to->engine_ms += w.engine_ms;
+  to->pred_ms += w.pred_ms;
+  to->batches += w.batches;
+  to->chain += w.chain;
+  to->barriers += w.barriers;
+  to->blocks = w.blocks;
+  to->prep_ms += w.prep_ms;
+}
+
+// Argument checks shared by every entry point (nothing is launched on
+// failure).  srcs / dsts are host arrays of base vertex ids.  A batch of
+// more queries than one launch holds (wave_queries) runs as consecutive
+// launches ("waves") of up to that many queries on the same workspace, each
+// on its own slice of dist, pred and h; the counters are summed.
+template <class W = IntW>
+og_status checked_run(const og_graph* g, const int32_t* srcs, int32_t nsrc, const int32_t* dsts, int32_t reps,
+                      bool multi, const int32_t* h, bool need_h, const og_schedule* s, int32_t* dist, int32_t* pred,
+                      void* ws, size_t ws_bytes, og_stats* stats, void* stream, bool force_delta1,
+                      int32_t* pred_edge = nullptr) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  auto fail = [&](og_status st) {
+    if (stats) stats->status = st;
+    return st;
+  };
+  if (!graph_ok(g) || !schedule_ok(s) || !dist || !ws || !srcs) return fail(OG_ERR_INVALID_ARG);
+  if (((uintptr_t)ws & 255) != 0) return fail(OG_ERR_INVALID_ARG);
+  if (need_h && !h) return fail(OG_ERR_INVALID_ARG);
+  if (pred_edge && !pred) return fail(OG_ERR_INVALID_ARG);
+  if (reps < 1 || reps > kMaxBatch || nsrc < 1) return fail(OG_ERR_INVALID_ARG);
+  for (int i = 0; i < nsrc; ++i)
+    if (srcs[i] < 0 || srcs[i] >= g->n) return fail(OG_ERR_INVALID_ARG);
+  if (dsts)
+    for (int q = 0; q < reps; ++q)
+      if (dsts[q] < 0 || dsts[q] >= g->n) return fail(OG_ERR_INVALID_ARG);
+  const int per = multi ? 1 : wave_queries(g->n);
+  if (multi || reps <= per) {
+    const Shape sh{reps, nsrc, dsts != nullptr};
+    if (!shape_ok(g, sh)) return fail(OG_ERR_INVALID_ARG);
+    std::vector<int> vs((size_t)nsrc), vt;
+    for (int i = 0; i < nsrc; ++i) vs[i] = multi ? srcs[i] : i * g->n + srcs[i];
+    if (dsts) {
+      vt.resize((size_t)reps);
+      for (int q = 0; q < reps; ++q) vt[q] = q * g->n + dsts[q];
+    }
+    return dispatch<W>(g, sh, vs, vt, h, s, dist, pred, pred_edge, ws, ws_bytes, stats, stream, force_delta1);
+  }
+  if (per < 1 || (s->flags & (OG_FLAG_VERTEX_BLOCKS | OG_FLAG_ASYNC))) return fail(OG_ERR_INVALID_ARG);
+  og_stats total;
+  std::memset(&total, 0, sizeof(total));
+  og_status st = OG_OK;
+  for (int q0 = 0; q0 < reps && st == OG_OK; q0 += per) {
+    const int nq = reps - q0 < per ? reps - q0 : per;
+    const Shape sh{nq, nq, dsts != nullptr};
+    std::vector<int> vs((size_t)nq), vt;
+    for (int i = 0; i < nq; ++i) vs[i] = i * g->n + srcs[q0 + i];
+    if (dsts) {
+      vt.resize((size_t)nq);
+      for (int q = 0; q < nq; ++q) vt[q] = q * g->n + dsts[q0 + q];
+    }
+    const size_t off = (size_t)q0 * (size_t)g->n;
+    og_stats ws_st;
+    std::memset(&ws_st, 0, sizeof(ws_st));
+    st = dispatch<W>(g, sh, vs, vt, h ? h + off : nullptr, s, dist + off, pred ? pred + off : nullptr, nullptr, ws,
+                     ws_bytes, &ws_st, stream, force_delta1);
+    add_stats(&total, ws_st);
+    if (total.status == OG_OK) total.status = st;
+  }
+  if (stats) *stats = total;
+  return st;
 }
 
 }  // namespace og
@@ -4282,7 +4357,10 @@ size_t og_workspace_bytes(const og_graph* g, const og_schedule* s) {
 }
 
 size_t og_workspace_bytes_batch(const og_graph* g, const og_schedule* s, int32_t nq) {
-  return ws_bytes_shape(g, s, og::Shape{nq, nq, true});
+  if (!og::graph_ok(g) || nq < 1 || nq > og::kMaxBatch) return 0;
+  const int per = og::wave_queries(g->n);
+  const int q = nq < per ? nq : per;  // a larger batch runs in waves of `per` queries
+  return ws_bytes_shape(g, s, og::Shape{q, q, true});
 }
 
 size_t og_workspace_bytes_multi(const og_graph* g, const og_schedule* s, int32_t nsrc) {

@@ -213,3 +213,77 @@ def test_multi_source_super_source_reduction(orc, road128):
     rd, _ = orc.sssp(big, g.n)
     assert np.array_equal(d, rd[:g.n])
     assert orc.check(big, g.n, np.concatenate([d, [0]]).astype(np.int32), None) == 0
+
+
+@pytest.mark.parametrize("fn", ["sssp", "ppsp", "astar"])
+def test_batch_waves_beyond_one_launch(orc, fn):
+    """A batch of more queries than one launch holds (1,024 per launch) runs
+    as consecutive launches on one workspace: 1,100 queries on the 64 x 64
+    grid (two launches), every sampled query exact, including both sides of
+    the cut, and the counters summed over the launches."""
+    side = 64
+    g = gg.road(side, seed=0)  # weights >= 10 * length: floor(10 * euclid) is admissible
+    dg = og.DeviceGraph.from_host(g, DEV)
+    nq = 1100
+    srcs = gg.pick_sources(g, nq, seed=31)
+    dsts = gg.pick_sources(g, nq, seed=32)
+    sched = og.Schedule(delta=64)
+    assert og.workspace_bytes(dg, sched, batch=nq) == og.workspace_bytes(dg, sched, batch=1024)
+    say(f"{fn}_batch waves nq={nq}")
+    if fn == "sssp":
+        d, p, st = og.sssp_batch(dg, srcs, sched)
+    elif fn == "ppsp":
+        d, p, st = og.ppsp_batch(dg, srcs, dsts, sched)
+    else:
+        hs = [gg.grid_heuristic_device(side, dsts[q0:q0 + 275], DEV) for q0 in range(0, nq, 275)]
+        h = torch.cat(hs).contiguous()
+        d, p, st = og.astar_batch(dg, srcs, dsts, h, sched)
+    torch.cuda.synchronize()
+    assert st["status"] == 0 and d.shape == (nq, g.n)
+    dn, pn = d.cpu().numpy(), p.cpu().numpy()
+    for q in (0, 511, 1023, 1024, 1050, 1099):
+        if fn == "sssp":
+            rd, rp = orc.sssp(g, int(srcs[q]))
+            assert np.array_equal(dn[q], rd) and np.array_equal(pn[q], rp), q
+        else:
+            want = orc.ppsp(g, int(srcs[q]), int(dsts[q]))
+            if want < 0:
+                assert dn[q, dsts[q]] == INF, q
+                continue
+            assert dn[q, dsts[q]] == want, q
+            assert walk(g, int(srcs[q]), int(dsts[q]), pn[q]) == want, q
+    if fn == "sssp":
+        assert st["reached_vertices"] == int(np.count_nonzero(dn != INF))
+
+
+def walk(g, s, t, pred):
+    v, total = t, 0
+    while v != s:
+        u = int(pred[v])
+        row = slice(g.row_ptr[u], g.row_ptr[u + 1])
+        idx = np.nonzero(g.col[row] == v)[0]
+        assert len(idx) >= 1
+        total += int(g.w[row][idx].min())
+        v = u
+    return total
+
+
+@pytest.mark.slow
+def test_road4096_batch256(orc):
+    """256 single-source queries on the full 4096^2 road-like grid in one
+    og_sssp_batch call (virtual ids 256 * n >= 2^31: launches of 127
+    queries), queries on both sides of each launch boundary compared with
+    the oracle element by element."""
+    g = gg.road(4096, seed=0)
+    dg = og.DeviceGraph.from_host(g, DEV)
+    srcs = [int(s) for s in gg.pick_sources(g, 256, seed=1)]
+    say("road4096 batch x256")
+    d, p, st = og.sssp_batch(dg, srcs, og.Schedule(delta=512, queue_capacity=127 * (1 << 21)))
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    for q in (0, 126, 127, 253, 254, 255):
+        ref_d, ref_p = orc.sssp(g, srcs[q])
+        assert np.array_equal(d[q].cpu().numpy(), ref_d), q
+        assert np.array_equal(p[q].cpu().numpy(), ref_p), q
+    del d, p
+    torch.cuda.empty_cache()
