@@ -14,6 +14,8 @@
 //            [--bins]   (degree-binned load balancing)
 //            [--split [--keep]]   (light/heavy edge split; --keep reuses the
 //                                  split copy across the calls)
+//            [--blocks [--block-size N]]   (LDS-resident vertex blocks, the
+//                                  blocked copy kept across the calls)
 //            [--copy-calibration]
 //
 // --copy-calibration instead runs a plain copy kernel over 1 GiB three
@@ -80,7 +82,8 @@ int main(int argc, char** argv) {
   int update = OG_EAGER_WITH_FUSION, engine = OG_ENGINE_PERSISTENT;
   bool rmat = false, kcore = false;
   uint32_t direction = 0;
-  bool bins = false, split = false, keep = false;
+  bool bins = false, split = false, keep = false, blocks = false;
+  int block_size = 0;
   for (int i = 1; i < argc; ++i) {
     auto next = [&](void) -> const char* {
       if (i + 1 >= argc) { std::fprintf(stderr, "missing value for %s\n", argv[i]); std::exit(2); }
@@ -112,6 +115,8 @@ int main(int argc, char** argv) {
     else if (!std::strcmp(argv[i], "--bins")) bins = true;
     else if (!std::strcmp(argv[i], "--split")) split = true;
     else if (!std::strcmp(argv[i], "--keep")) keep = true;
+    else if (!std::strcmp(argv[i], "--blocks")) blocks = true;
+    else if (!std::strcmp(argv[i], "--block-size")) block_size = std::atoi(next());
     else if (!std::strcmp(argv[i], "--copy-calibration")) return copy_calibration();
     else { std::fprintf(stderr, "unknown argument %s\n", argv[i]); return 2; }
   }
@@ -152,7 +157,8 @@ int main(int argc, char** argv) {
   s.update = update;
   s.engine = engine;
   s.flags = OG_FLAG_TIMING | direction | (bins ? OG_FLAG_DEGREE_BINS : 0u) | (split ? OG_FLAG_LIGHT_HEAVY : 0u) |
-            (split && keep ? OG_FLAG_KEEP_SPLIT : 0u);
+            (split && keep ? OG_FLAG_KEEP_SPLIT : 0u) | (blocks ? OG_FLAG_VERTEX_BLOCKS | OG_FLAG_KEEP_BLOCKS : 0u);
+  if (block_size > 0) s.block_size = block_size;
   if (window > 0) s.window_buckets = window;
   const size_t wsb = kcore ? og_workspace_bytes_kcore(&g, &s) : og_workspace_bytes(&g, &s);
   void* ws = nullptr;
