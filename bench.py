@@ -753,6 +753,9 @@ def main() -> int:
         "relaxations_per_query": int(np.mean([s["relaxations"] for s in stats])),
         "improvements_per_query": int(np.mean([s["improvements"] for s in stats])),
         "pushes_per_query": int(np.mean([s["pushes_local"] + s["pushes_global"] for s in stats])),
+        # global-queue entries in use at once (whole 4,096-entry chunks) and the workspace
+        "queue_pool_peak_entries": int(max(s["pool_needed"] for s in stats)),
+        "workspace_bytes": int(og.workspace_bytes(dg, fused)),
         "variants": variants,
         "cpu_baseline": cpu,
         "parity_on_cpu_sample": parity,

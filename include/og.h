@@ -62,9 +62,12 @@ typedef int32_t og_status;
 #define OG_ERR_INVALID_ARG (-1)     /* bad argument; nothing was launched       */
 #define OG_ERR_NEGATIVE_WEIGHT (-2) /* an edge weight < 0 was found             */
 #define OG_ERR_OVERFLOW (-3)        /* a path length reached INT32_MAX          */
-#define OG_ERR_WORKSPACE (-4)       /* ws_bytes too small, or a queue filled up;
+#define OG_ERR_WORKSPACE (-4)       /* ws_bytes too small, a queue filled up or
+                                       the queue pool ran empty;
                                        og_stats.queue_needed tells how many
-                                       entries per queue would have been used  */
+                                       entries per queue would have been used,
+                                       og_stats.pool_needed how many pool
+                                       entries were in use                     */
 #define OG_ERR_HIP (-5)             /* a HIP runtime call failed                */
 #define OG_ERR_ROUND_LIMIT (-6)     /* schedule.max_rounds reached              */
 #define OG_ERR_INTERNAL (-7)        /* an internal consistency check failed
@@ -227,6 +230,11 @@ typedef struct og_schedule {
   int32_t block_size;       /* OG_FLAG_VERTEX_BLOCKS: mean block size the
                                partition aims at, in vertices (0 = 2048; at
                                most 4096)                                     */
+  int64_t queue_pool;       /* entries shared by all global queues, drawn in
+                               chunks of 4096 as the queues grow and returned
+                               when a queue has been consumed (0 = twice
+                               queue_capacity plus one chunk per queue); an
+                               empty pool ends the call with OG_ERR_WORKSPACE */
 } og_schedule;
 
 /* Per-call counters (host struct). */
@@ -257,6 +265,9 @@ typedef struct og_stats {
                                activations of blocks are counted in batches)  */
   double prep_ms;           /* OG_FLAG_VERTEX_BLOCKS with OG_FLAG_TIMING: time
                                to build the blocked copy (0 when kept)        */
+  int64_t pool_needed;      /* most queue-pool entries in use at once (whole
+                               chunks; after OG_ERR_WORKSPACE: the demand up
+                               to the failure)                               */
 } og_stats;
 
 /* Library version, (major << 16) | minor. */
@@ -412,8 +423,8 @@ og_status og_read_stats(const void* ws, og_stats* stats, void* stream);
  * creates no HIP object, so OG_FLAG_TIMING and OG_ENGINE_GRAPH_ROUNDS are
  * rejected (OG_ERR_INVALID_ARG); a graph and schedule whose
  * og_workspace_bytes() exceed OG_SCRATCH_BYTES return OG_ERR_WORKSPACE
- * with nothing launched (a smaller schedule.queue_capacity shrinks the
- * need).  Every call on one device uses the same array and leaves its
+ * with nothing launched (a smaller schedule.queue_capacity or queue_pool
+ * shrinks the need).  Every call on one device uses the same array and leaves its
  * contents behind (each call initialises what it reads): calls that
  * overlap in time on one device race and must not be made.  Results are
  * those of og_sssp. */

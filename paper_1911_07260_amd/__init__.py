@@ -72,6 +72,7 @@ class Schedule:
     bin_thread: int = 0
     bin_wave: int = 0
     block_size: int = 0
+    queue_pool: int = 0
 
     @property
     def fused(self) -> bool:

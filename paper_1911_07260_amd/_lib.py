@@ -77,6 +77,7 @@ class OgSchedule(ctypes.Structure):
         ("bin_thread", ctypes.c_int32),
         ("bin_wave", ctypes.c_int32),
         ("block_size", ctypes.c_int32),
+        ("queue_pool", ctypes.c_int64),
     ]
 
 
@@ -102,6 +103,7 @@ class OgStats(ctypes.Structure):
         ("barriers", ctypes.c_int64),
         ("blocks", ctypes.c_int64),
         ("prep_ms", ctypes.c_double),
+        ("pool_needed", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -83,6 +83,15 @@ constexpr int kFlags = 64;  // release flags, one per 128-byte line
 constexpr int kMaxQueries = 1024;    // queries in one launch
 constexpr int kMaxBatch = 1 << 20;  // queries in one batch call (in launches of at most kMaxQueries)
 constexpr size_t kCtlBytes = 65536;
+// The global bucket lists (K window slots, 2 spill lists, 2 far lists) draw
+// fixed-size chunks from one shared pool: list L's position p lives in the
+// chunk its table names for p / kChunk.  A list's chunks go back to the
+// pool when the list is consumed.
+constexpr int kChunkLog = 12;
+constexpr unsigned kChunk = 1u << kChunkLog;  // entries per chunk (32 KB)
+constexpr int kNoChunk = -1;    // table entry: chunk not taken yet
+constexpr int kLostChunk = -2;  // table entry: the pool was empty (the call fails)
+constexpr unsigned kChunkSpinLimit = 1u << 20;  // polls before a missing chunk is an internal error
 constexpr unsigned kNoBucket = 0xffffffffu;
 constexpr int kInf = INT_MAX;
 constexpr int kPeeled = INT_MAX;  // k-core mark of a peeled vertex (above every generation)
@@ -186,6 +195,8 @@ struct Ctl {
   Word64 sym;          // symmetry checksum of OG_FLAG_VALIDATE with a pull direction
   Word slices;         // pull direction: row slices listed per copy of the graph
   Word64 pred_slices;  // predecessor pass: slices of long rows listed
+  Word free_top;       // free chunks on the pool's stack
+  Word pool_peak;      // most chunks taken at once (sampled at each bucket decision)
   Word blk_out;        // vertex blocks: work items of the round not yet finished
   Word blk_head;       // vertex blocks: ring positions taken
   Word blk_tail;       // vertex blocks: ring positions filled
@@ -207,15 +218,17 @@ struct Args {
   unsigned delta;
   int shift;  // log2(delta) when delta is a power of two, else -1
   int K;      // window buckets (power of two)
-  unsigned cap;
+  unsigned cap;  // entries one list may hold
   int fused;
   unsigned threshold;
   unsigned max_rounds;
   int nwg;
   Ctl* ctl;
-  int2* win;
-  int2* spill;
-  int2* far;
+  int2* pool;         // [pool_chunks * kChunk] entries of every global list
+  int* ctab;          // [(K + 4) * tchunks] chunk of each list position / kChunk
+  int* fstack;        // [pool_chunks] free chunks (the bottom free_top entries)
+  unsigned pool_chunks;
+  unsigned tchunks;   // table entries per list: ceil(cap / kChunk)
   int lazy;       // lazy bucket update: record changes, file them after a barrier
   int* aux;       // [n] lazy: change flag (SSSP) or lost-neighbour count (k-core)
   int* buf;       // [buf_cap] lazy: vertices changed this round, each once
@@ -457,9 +470,48 @@ struct BlockW : IntW {
   static constexpr bool kBlocks = true;
 };
 
-__device__ __forceinline__ int2* list_ptr(const Args& a, int kind, int index) {
-  int2* base = kind == kInWin ? a.win : (kind == kInSpill ? a.spill : a.far);
-  return base + (size_t)index * a.cap;
+// List ids: window slots 0 .. K-1, spill lists K, K+1, far lists K+2, K+3.
+__device__ __forceinline__ int list_of(const Args& a, int kind, int index) {
+  return kind == kInWin ? index : (kind == kInSpill ? a.K + index : a.K + 2 + index);
+}
+__device__ __forceinline__ unsigned* chunk_slot(const Args& a, int list, unsigned pos) {
+  return reinterpret_cast<unsigned*>(a.ctab) + (size_t)list * a.tchunks + (pos >> kChunkLog);
+}
+
+// Entry pos of a list, written before the last device-wide barrier (so its
+// chunk is in the table); a chunk the pool could not supply reads as no
+// entry (the call has already failed).
+__device__ __forceinline__ int2 load_at(const Args& a, int list, unsigned pos) {
+  const int ch = (int)ld_dev(chunk_slot(a, list, pos));
+  if (ch < 0) return make_int2(-1, 0);
+  return ld_entry(a.pool, (size_t)ch * kChunk + (pos & (kChunk - 1)));
+}
+
+// Stores (v, d) at position pos (< cap) of a list.  The writer of a chunk's
+// first position takes a chunk from the pool for it; writers of the chunk's
+// other positions wait until the table names it (that writer reserved its
+// position earlier and does not wait on anything).  False when the pool was
+// empty (OG_ERR_WORKSPACE is set).
+__device__ bool store_at(const Args& a, int list, unsigned pos, int v, int d) {
+  unsigned* slot = chunk_slot(a, list, pos);
+  if ((pos & (kChunk - 1)) == 0) {
+    const int top = atomicSub(reinterpret_cast<int*>(&a.ctl->free_top.v), 1) - 1;
+    int ch = kLostChunk;
+    if (top >= 0 && top < (int)a.pool_chunks) ch = (int)ld_dev(reinterpret_cast<const unsigned*>(a.fstack) + top);
+    else set_status(a.ctl, OG_ERR_WORKSPACE);
+    st_dev(slot, (unsigned)ch);
+  }
+  int ch;
+  for (unsigned spin = 0; (ch = (int)ld_dev(slot)) == kNoChunk; ++spin) {
+    if (spin == kChunkSpinLimit) {
+      set_status(a.ctl, OG_ERR_INTERNAL);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (ch < 0) return false;
+  st_entry(a.pool, (size_t)ch * kChunk + (pos & (kChunk - 1)), v, d);
+  return true;
 }
 
 // Block-wide exclusive prefix sum of x; *total receives the sum.  The
@@ -503,16 +555,16 @@ __device__ void wave_push_global(const Args& a, const S& s, Counters& c, bool ha
     const bool mine = has && tgt == t;
     const unsigned long long mm = __ballot(mine);
     unsigned* tail;
-    int2* q;
+    int list;
     if (t < K) {
       tail = &ctl->win_tail[t].v;
-      q = a.win + (size_t)t * a.cap;
+      list = t;
     } else if (t == K) {
       tail = &ctl->spill_tail[s.spill_out].v;
-      q = a.spill + (size_t)s.spill_out * a.cap;
+      list = K + s.spill_out;
     } else {
       tail = &ctl->far_tail[s.far_out].v;
-      q = a.far + (size_t)s.far_out * a.cap;
+      list = K + 2 + s.far_out;
     }
     unsigned base = 0;
     if ((int)lane_id() == leader) base = atomicAdd(tail, (unsigned)__popcll(mm));
@@ -520,11 +572,12 @@ __device__ void wave_push_global(const Args& a, const S& s, Counters& c, bool ha
     if (mine) {
       const unsigned pos = base + (unsigned)__popcll(mm & lanemask_lt());
       if (pos < a.cap && pos >= base) {
-        st_entry(q, pos, v, d);
-        c.push_global++;
-        if (t == K + 1) {
-          c.far++;
-          atomicMin(&ctl->far_min[s.far_out].v, b);
+        if (store_at(a, list, pos, v, d)) {
+          c.push_global++;
+          if (t == K + 1) {
+            c.far++;
+            atomicMin(&ctl->far_min[s.far_out].v, b);
+          }
         }
         has = false;
       } else if (t == K + 1) {
@@ -1237,7 +1290,7 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
   if (tid == 0) s.gbase = atomicAdd(&a.ctl->spill_tail[s.spill_out].v, cnt);
   __syncthreads();
   const unsigned gb = s.gbase;
-  int2* q = a.spill + (size_t)s.spill_out * a.cap;
+  const int list = a.K + s.spill_out;
   for (unsigned i0 = 0; i0 < cnt; i0 += kBlock) {
     const unsigned i = i0 + tid;
     bool spill_far = false;
@@ -1246,8 +1299,7 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
       e = s.lq[(h + i) & (kLq - 1)];
       const unsigned pos = gb + i;
       if (pos < a.cap && pos >= gb) {
-        st_entry(q, pos, e.x, e.y);
-        c.push_global++;
+        if (store_at(a, list, pos, e.x, e.y)) c.push_global++;
       } else {
         spill_far = true;
       }
@@ -1265,8 +1317,9 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
 template <class W>
 __device__ void run_round(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
-  const int2* in = W::kSplit && s.in_kind == kInHeavy ? a.heavy + (size_t)s.in_index * a.hcap
-                                                      : list_ptr(a, s.in_kind, s.in_index);
+  // the round input: a heavy list (light/heavy split) or a pooled list
+  const int2* hin = W::kSplit && s.in_kind == kInHeavy ? a.heavy + (size_t)s.in_index * a.hcap : nullptr;
+  const int in_list = list_of(a, s.in_kind, s.in_index);
   const unsigned count = s.in_count;
   const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
   const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
@@ -1322,7 +1375,8 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
       if (mode == 1) {
         ent = s.lq[(s.bhead + tid) & (kLq - 1)];
       } else {
-        const int2 e = ld_entry(in, (size_t)s.gbase + tid);
+        const unsigned pos = s.gbase + (unsigned)tid;
+        const int2 e = hin ? ld_entry(hin, pos) : load_at(a, in_list, pos);
         ent = make_int4(e.x, e.y, 0, 0);
       }
     }
@@ -1357,7 +1411,7 @@ __device__ __forceinline__ void mark_peeled(const Args& a, int v) {
 // in the bitmap.
 template <class W>
 __device__ void run_mark(const Args& a, Smem& s, Counters& c) {
-  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const int in_list = list_of(a, s.in_kind, s.in_index);
   const unsigned count = s.in_count;
   const unsigned cur = s.cur;
   const int stamp = pull_stamp(s);
@@ -1366,8 +1420,8 @@ __device__ void run_mark(const Args& a, Smem& s, Counters& c) {
     bool later = false;
     int v = 0, d = 0;
     unsigned rb = 0;
-    if (i < count) {
-      const int2 e = ld_entry(in, i);
+    const int2 e = i < count ? load_at(a, in_list, i) : make_int2(-1, 0);
+    if (e.x >= 0) {
       v = e.x;
       d = e.y;
       const int now = (int)ld_dev(reinterpret_cast<const unsigned*>(a.dist) + v);
@@ -1625,7 +1679,7 @@ __device__ void run_pull(const Args& a, Smem& s, Counters& c) {
 template <class W>
 __device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
-  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const int in_list = list_of(a, s.in_kind, s.in_index);
   const unsigned count = s.in_count;
   const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
   const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
@@ -1694,7 +1748,7 @@ __device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
       if (mode == 1) {
         ent = s.lq[(bhead + tid) & (kLq - 1)];
       } else {
-        const int2 e = ld_entry(in, (size_t)s.gbase + tid);
+        const int2 e = load_at(a, in_list, s.gbase + (unsigned)tid);
         ent = make_int4(e.x, e.y, 0, 0);
       }
     }
@@ -1761,6 +1815,41 @@ __device__ void decide(const Args& a) {
   }
   const unsigned slot_cur_cnt = __shfl(wraw, 0);
   const unsigned long long ne = __ballot(nonempty) & ~1ull;  // buckets after cur
+  // The consumed input list's chunks go back to the pool (every lane takes a
+  // share of its chunk table).  After a failure the call ends and the pool is
+  // rebuilt by the next one.
+  if (!(W::kSplit && in_kind == kInHeavy)) {
+    const unsigned* tail = in_kind == kInWin ? &c->win_tail[in_index].v
+                         : in_kind == kInSpill ? &c->spill_tail[in_index].v
+                                               : &c->far_tail[in_index].v;
+    const unsigned raw = ld_dev(tail);
+    const unsigned used = raw < a.cap ? raw : a.cap;
+    const unsigned nch = (used + kChunk - 1) >> kChunkLog;
+    const int top = (int)ld_dev(&c->free_top.v);
+    if (lane == 0) {
+      const unsigned taken = (unsigned)((int)a.pool_chunks - top);
+      if (taken > ld_dev(&c->pool_peak.v)) st_dev(&c->pool_peak.v, taken);
+    }
+    if (status == 0) {
+      unsigned* tab = chunk_slot(a, list_of(a, in_kind, in_index), 0);
+      bool bad = top < 0 || (unsigned)top + nch > a.pool_chunks;
+      for (unsigned j = (unsigned)lane; j < nch && !bad; j += kWave) {
+        const int ch = (int)ld_dev(tab + j);
+        if (ch < 0 || (unsigned)ch >= a.pool_chunks) {
+          bad = true;
+        } else {
+          st_dev(reinterpret_cast<unsigned*>(a.fstack) + top + j, (unsigned)ch);
+          st_dev(tab + j, (unsigned)kNoChunk);
+        }
+      }
+      if (__ballot(bad)) {
+        status = OG_ERR_INTERNAL;  // a chunk table disagrees with its list's fill
+        if (lane == 0) set_status(c, status);
+      } else if (lane == 0) {
+        st_dev(&c->free_top.v, (unsigned)(top + (int)nch));
+      }
+    }
+  }
   if (lane != 0) return;
   // the consumed input list is empty again
   if (in_kind == kInWin) st_dev(&c->win_tail[in_index].v, 0);
@@ -1981,7 +2070,8 @@ __global__ __launch_bounds__(kBlock) void k_init_sources(Args a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.nsrc; i += gridDim.x * blockDim.x) {
     const int s = a.srcs[i];
     a.dist[s] = 0;
-    st_entry(a.far, (size_t)i, s, 0);
+    // far list 0's first chunks are chunks 0, 1, ... of the pool (k_pool_init)
+    st_entry(a.pool, (size_t)i, s, 0);
     atomicMin(&c->far_min[0].v, W::bucket(a, W::key(a, s, 0)));
   }
 }
@@ -2068,7 +2158,7 @@ __global__ __launch_bounds__(kBlock) void k_init_core(Args a) {
     a.dist[v] = d;
     a.mark[v] = 0;
     if (a.aux) a.aux[v] = 0;
-    st_entry(a.far, (size_t)v, (int)v, d);
+    st_entry(a.pool, (size_t)v, (int)v, d);  // far list 0: pool chunks 0, 1, ...
     lo = (unsigned)d < lo ? (unsigned)d : lo;
   }
   for (int o = 32; o >= 1; o >>= 1) {
@@ -2076,6 +2166,27 @@ __global__ __launch_bounds__(kBlock) void k_init_core(Args a) {
     lo = y < lo ? y : lo;
   }
   if (lane_id() == 0 && lo != kNoBucket) atomicMin(&a.ctl->far_min[0].v, lo);
+}
+
+// The queue pool at the start of a call: every chunk table entry empty but
+// far list 0's first `pre` (chunks 0 .. pre-1, where the sources or, for
+// k-core, all vertices are filed), the other chunks on the free stack.  Runs
+// after the control block is zeroed.
+__global__ __launch_bounds__(kBlock) void k_pool_init(Args a, unsigned pre) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  const unsigned long long ntab = (unsigned long long)(a.K + 4) * a.tchunks;
+  const int far0 = a.K + 2;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntab; i += stride) {
+    const unsigned j = (unsigned)(i % a.tchunks);
+    a.ctab[i] = (int)(i / a.tchunks) == far0 && j < pre ? (int)j : kNoChunk;
+  }
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.pool_chunks - pre;
+       i += stride)
+    a.fstack[i] = (int)(pre + i);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->free_top.v = a.pool_chunks - pre;
+    a.ctl->pool_peak.v = pre;
+  }
 }
 
 __global__ void k_init_ctl(Args a) {
@@ -2684,7 +2795,7 @@ __device__ void blk_process(const Args& a, BlkSmem& s, Counters& c, int b) {
 template <class W>
 __device__ void run_round_blocks(const Args& a, BlkSmem& s, Counters& c) {
   const int tid = threadIdx.x;
-  const int2* in = list_ptr(a, s.in_kind, s.in_index);
+  const int in_list = list_of(a, s.in_kind, s.in_index);
   const unsigned count = s.in_count;
   const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
   const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
@@ -2716,10 +2827,10 @@ __device__ void run_round_blocks(const Args& a, BlkSmem& s, Counters& c) {
     if (s.mode == 0) break;
     int v = -1, d = 0;
     if (tid < s.nb) {
-      const int2 e = ld_entry(in, (size_t)s.gbase + tid);
+      const int2 e = load_at(a, in_list, s.gbase + (unsigned)tid);
       v = e.x;
       d = e.y;
-      if ((unsigned)v >= (unsigned)a.n) {
+      if (v >= 0 && v >= a.n) {
         set_status(a.ctl, OG_ERR_INTERNAL);
         v = -1;
       }
@@ -3494,6 +3605,40 @@ size_t table_bytes(const Shape& sh) {
   return (b + 255) & ~(size_t)255;
 }
 
+// The global lists' pool, from byte offset off: the chunk tables (one per
+// list, tchunks entries each), the free stack and the chunks.  Far list 0
+// starts with chunks 0 .. pre-1, which hold the sources (k-core: every
+// vertex).  Pool size: schedule.queue_pool entries rounded up to whole
+// chunks, by default twice one list's capacity plus one chunk per list (the
+// partly filled last chunks), never more than every list full at once, and
+// never fewer than the sources' chunks plus one.
+struct PoolLayout {
+  unsigned tchunks, chunks, pre;
+  size_t ctab, fstack, pool, end;
+};
+
+PoolLayout pool_layout(const og_schedule* r, const Shape& sh, long long cap, size_t off) {
+  PoolLayout L;
+  const long long ck = (long long)kChunk;
+  const long long lists = (long long)r->window_buckets + 4;  // K window slots, 2 spill, 2 far
+  L.tchunks = (unsigned)((cap + ck - 1) / ck);
+  L.pre = (unsigned)(((long long)sh.nsrc + ck - 1) / ck);
+  long long ch = r->queue_pool > 0 ? (r->queue_pool + ck - 1) / ck : (2 * cap + ck - 1) / ck + lists;
+  if (ch > lists * (long long)L.tchunks) ch = lists * (long long)L.tchunks;
+  if (ch < (long long)L.pre + 1) ch = (long long)L.pre + 1;
+  L.chunks = (unsigned)ch;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  L.ctab = take(sizeof(int) * (size_t)lists * L.tchunks);
+  L.fstack = take(sizeof(int) * (size_t)L.chunks);
+  L.pool = take(sizeof(int2) * (size_t)L.chunks * kChunk);
+  L.end = off;
+  return L;
+}
+
 bool split_on(const og_schedule* r, const Shape& sh) { return !sh.core && (r->flags & OG_FLAG_LIGHT_HEAVY); }
 bool blocks_on(const og_schedule* r, const Shape& sh) { return !sh.core && (r->flags & OG_FLAG_VERTEX_BLOCKS); }
 
@@ -3559,9 +3704,7 @@ size_t vec_bytes(long long n) { return ((size_t)n * sizeof(int) + 255) & ~(size_
 
 size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   const long long cap = queue_cap(g, r, sh);
-  const size_t lists = (size_t)r->window_buckets + 4;  // K window slots, 2 spill, 2 far
-  size_t b = kCtlBytes + table_bytes(sh) + lists * (size_t)cap * sizeof(int2);
-  b = (b + 255) & ~(size_t)255;
+  size_t b = pool_layout(r, sh, cap, kCtlBytes + table_bytes(sh)).end;
   const long long nv = (long long)sh.reps * g->n;
   if (r->update == OG_LAZY_UPDATE) b += 2 * vec_bytes(nv);
   if (sh.core) b += vec_bytes(nv);
@@ -3586,7 +3729,7 @@ bool schedule_ok(const og_schedule* s) {
   if (s->window_buckets == 1) return false;
   if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS && s->engine != OG_ENGINE_GRAPH_ROUNDS)
     return false;
-  if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0) return false;
+  if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0 || s->queue_pool < 0) return false;
   if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL |
                    OG_FLAG_HYBRID_DIRECTION | OG_FLAG_DEGREE_BINS | OG_FLAG_KEEP_SPLIT | OG_FLAG_VERTEX_BLOCKS |
                    OG_FLAG_KEEP_BLOCKS))
@@ -3633,6 +3776,7 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   st->reached_vertices = (int64_t)h.st[kStReachedV].v;
   st->reached_edges = (int64_t)h.st[kStReachedE].v;
   st->queue_needed = (int64_t)h.need.v;
+  st->pool_needed = (int64_t)h.pool_peak.v * kChunk;
   st->batches = (int64_t)h.st[kStBatches].v;
   st->chain = (int64_t)h.st[kStChain].v;
   st->barriers = (int64_t)h.c.epoch;
@@ -3891,12 +4035,14 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   a.max_rounds = (unsigned)r.max_rounds;
   a.nwg = nwg;
   a.ctl = (Ctl*)base;
-  a.win = (int2*)(base + kCtlBytes + table_bytes(sh));
-  a.spill = a.win + (size_t)a.K * (size_t)cap;
-  a.far = a.spill + 2 * (size_t)cap;
+  const PoolLayout pl = pool_layout(&r, sh, cap, kCtlBytes + table_bytes(sh));
+  a.ctab = (int*)(base + pl.ctab);
+  a.fstack = (int*)(base + pl.fstack);
+  a.pool = (int2*)(base + pl.pool);
+  a.pool_chunks = pl.chunks;
+  a.tchunks = pl.tchunks;
   {
-    size_t off = kCtlBytes + table_bytes(sh) + ((size_t)a.K + 4) * (size_t)cap * sizeof(int2);
-    off = (off + 255) & ~(size_t)255;
+    size_t off = pl.end;
     a.lazy = r.update == OG_LAZY_UPDATE;
     a.aux = nullptr;
     a.buf = nullptr;
@@ -3996,13 +4142,17 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   }
   const int fill_grid = di.cus * 8;
   const int src_grid = (sh.nsrc + kBlock - 1) / kBlock;
+  const int pool_grid = (int)std::min<long long>(
+      fill_grid, ((long long)std::max<size_t>((size_t)(a.K + 4) * pl.tchunks, pl.chunks) + kBlock - 1) / kBlock);
   if constexpr (W::kCore) {
     hipLaunchKernelGGL(k_zero_ctl, dim3(16), dim3(kBlock), 0, stream, a.ctl);
     hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
+    hipLaunchKernelGGL(k_pool_init, dim3(pool_grid), dim3(kBlock), 0, stream, a, pl.pre);
     hipLaunchKernelGGL(k_init_core, dim3(fill_grid), dim3(kBlock), 0, stream, a);
   } else {
     hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int)W::kInfBits);
     hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
+    hipLaunchKernelGGL(k_pool_init, dim3(pool_grid), dim3(kBlock), 0, stream, a, pl.pre);
     hipLaunchKernelGGL(k_init_sources<PW>, dim3(src_grid), dim3(kBlock), 0, stream, a);
   }
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);
@@ -4125,15 +4275,15 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
     int2* longs = nullptr;
     unsigned long long* sum = nullptr;
     const unsigned long long sw = ((unsigned long long)a.n + 63) / 64;  // summary words
-    if ((size_t)(a.K + 4) * a.cap >= lcap + sw) {
-      longs = a.win;
+    if ((size_t)a.pool_chunks * kChunk >= lcap + sw) {
+      longs = a.pool;
       hipLaunchKernelGGL(k_fill, dim3(1), dim3(kWave), 0, stream, (int*)&a.ctl->pred_slices.v, 2ll, 0);
       // The parity filter pays where a vertex's neighbours are scattered and
       // their dist reads miss the cache, which mean degree >= kPredParDeg
       // stands for (power-law graphs; a road grid's neighbours are local and
       // the extra read only adds latency there).
       if (g->m >= (long long)kPredParDeg * a.nbase) {
-        sum = reinterpret_cast<unsigned long long*>(a.win + lcap);
+        sum = reinterpret_cast<unsigned long long*>(a.pool + lcap);
         hipLaunchKernelGGL(k_pred_summary, dim3(fill_grid), dim3(kBlock), 0, stream, a, sum);
       }
     }
@@ -4240,6 +4390,7 @@ void add_stats(og_stats* to, const og_stats& w) {
   to->reached_vertices += w.reached_vertices;
   to->reached_edges += w.reached_edges;
   to->queue_needed = w.queue_needed > to->queue_needed ? w.queue_needed : to->queue_needed;
+  to->pool_needed = w.pool_needed > to->pool_needed ? w.pool_needed : to->pool_needed;
   to->init_ms += w.init_ms;
   to->engine_ms += w.engine_ms;
   to->pred_ms += w.pred_ms;

@@ -65,6 +65,24 @@ def _fake_graph(n=10, m=20):
     return _lib.OgGraph(n, m, 0x1000, 0x2000, 0x3000)
 
 
+def _queues(cap, k, nsrc=1, pool=0):
+    """Bytes of the global queues: per-queue chunk tables, the free stack and
+    the pool of 4,096-entry chunks (default: twice one queue's capacity plus
+    one chunk per queue, at most every queue full, at least the sources'
+    chunks plus one), each region 256-byte aligned."""
+    ck = 4096
+    lists = k + 4
+    tch = -(-cap // ck)
+    pre = -(-nsrc // ck)
+    ch = -(-pool // ck) if pool > 0 else -(-2 * cap // ck) + lists
+    ch = max(min(ch, lists * tch), pre + 1)
+
+    def v(nbytes):
+        return (nbytes + 255) // 256 * 256
+
+    return v(4 * lists * tch) + v(4 * ch) + v(8 * ch * ck)
+
+
 def test_workspace_bytes():
     lib = _lib.load()
     g = _fake_graph(1000, 4000)
@@ -72,14 +90,21 @@ def test_workspace_bytes():
     b = lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s))
     assert b % 256 == 0 and b >= 65536 + (16 + 4) * 1024 * 8
     s2 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000).to_c()
-    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 65536 + 256 + 12 * 5000 * 8
+    Q = _queues(5000, 8)
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 65536 + 256 + Q
+    # an explicit pool size, rounded up to whole chunks and clamped to the queues' total
+    for pool, want in ((1, 2), (9000, 3), (10 ** 9, 24)):
+        sp = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, queue_pool=pool).to_c()
+        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(sp)) == 65536 + 256 + _queues(5000, 8, pool=pool)
+        assert _queues(5000, 8, pool=pool) == 256 + (4 * want + 255) // 256 * 256 + 8 * 4096 * want
+    neg = og.Schedule(delta=4, queue_pool=-1).to_c()
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(neg)) == 0
     # lazy update: + change flags and change buffer, one int per vertex each
     s3 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, update=og.OG_LAZY_UPDATE).to_c()
     vec = (g.n * 4 + 255) // 256 * 256
-    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s3)) == 65536 + 256 + 12 * 5000 * 8 + 2 * vec
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s3)) == 65536 + 256 + Q + 2 * vec
     # k-core: no source table; + peel marks (and the lazy arrays)
-    base = 65536 + 12 * 5000 * 8
-    base = (base + 255) // 256 * 256
+    base = 65536 + Q
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s2)) == base + vec
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s3)) == base + 3 * vec
     # light/heavy split: + split copy of col and w, light counts, long-row
@@ -89,7 +114,7 @@ def test_workspace_bytes():
     for gs in (g, _fake_graph(1000, 100_000)):
         evec = (gs.m * 4 + 255) // 256 * 256
         hvec = ((gs.n + gs.m // 4096 + 1) * 4 + 255) // 256 * 256
-        assert lib.og_workspace_bytes(ctypes.byref(gs), ctypes.byref(s4)) == (65536 + 256 + 12 * 5000 * 8
+        assert lib.og_workspace_bytes(ctypes.byref(gs), ctypes.byref(s4)) == (65536 + 256 + Q
                                                                               + 2 * evec + 3 * vec + 4 * hvec)
     # pull direction (lazy only): + frontier marks (SSSP: 8 bytes per vertex; k-core: one bit) and the
     # long rows' slice list
@@ -98,7 +123,7 @@ def test_workspace_bytes():
         marks = (g.n * 8 + 255) // 256 * 256
         bits = ((g.n + 31) // 32 * 4 + 255) // 256 * 256
         slices = ((g.m // 2048 + g.m // 8192 + 1) * 8 + 255) // 256 * 256
-        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s5)) == (65536 + 256 + 12 * 5000 * 8 + 2 * vec
+        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s5)) == (65536 + 256 + Q + 2 * vec
                                                                              + marks + slices)
         assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s5)) == base + 3 * vec + bits + slices
     lazy_split = og.Schedule(delta=4, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_LIGHT_HEAVY).to_c()
