@@ -3,18 +3,22 @@
 Workload: 4096 x 4096 road-like grid (16,777,216 vertices, ~50.4 M directed
 edges; each grid edge kept with p = 0.75, 0.1 % long-range edges within 64
 grid steps, weights llround(10 * length * U(1, 2))), seed 0; 8 sources drawn
-with seed 1.  One step = one full single-source query through the C ABI:
-initialisation, the bucket engine (all rounds; fused, Delta 512, degree-
-binned load balancing) and the canonical predecessor pass, with the graph
-already resident in HBM.
+with seed 1.  One step = the whole workload through the C ABI: all 8
+sources in one og_sssp_batch launch (initialisation, the bucket engine over
+all rounds, fused, Delta 1024, degree-binned load balancing, and the
+canonical predecessor pass of every query), with the graph already resident
+in HBM.  The same sources one query per launch (Delta 512) are reported
+beside it as the serial figure.
 
 Prints one JSON line.  `value` is whole-job GTEPS = (sum over timed steps of
-the out-degrees of reached vertices) / wall time of the timed steps.
+the out-degrees of reached vertices, all queries) / wall time of the timed
+steps.
 
-Extra legs (outside the timed region): unfused, host-driven, lazy and
-flat-expansion variants on the same sources, a batched launch, the CPU
-oracle on a bounded sample (cpu_baseline), and bit-exact parity of the GPU
-distances on those sampled sources.
+Extra legs (outside the timed region): unfused, host-driven, lazy, flat-
+expansion and vertex-block variants one query per launch on the same
+sources, larger batched launches, the CPU oracle on a bounded sample
+(cpu_baseline), and bit-exact parity of the GPU distances and predecessors
+of the batched and the serial schedule on every source.
 
     python bench.py [--steps K] [--warmup W] [--delta D] [--no-cpu]
     python bench.py --copy-calibration   # plain 1 GiB device copy, for PMC scaling
@@ -50,7 +54,8 @@ PAPER_CONTEXT = {
     "source": "section 6, tables of per-source times, fusion impact and eager vs lazy",
 }
 ROAD_WEIGHTS = "w=max(llround(10*len*U(1,2)), ceil(10*len)) (the clamp keeps h=floor(10*euclid) admissible)"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_road4096_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_road4096_traffic.txt")  # one query per launch
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_road4096_batch8_traffic.txt")  # 8 per launch
 ENGINE_SRC = os.path.join(ROOT, "paper_1911_07260_amd", "csrc", "og_engine.hip")
 
 
@@ -69,17 +74,21 @@ def engine_hash(text: str | None = None) -> str:
     return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
-def read_traffic(delta: int):
-    """HBM bytes per k_persistent launch from the committed PMC summary, or
-    None when it is missing or was taken on a different kernel source or
-    schedule."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(delta: int, batch: int = 1):
+    """HBM bytes per k_persistent launch of `batch` queries from the committed
+    PMC summary, or None when it is missing or was taken on a different
+    kernel source, Delta or batch size."""
+    path = TRAFFIC_FILE if batch == 1 else BATCH_TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_FILE).read()
+    text = open(path).read()
     h = re.search(r"engine_code_sha256_16:\s*(\w+)", text)
     d = re.search(r"delta:\s*(\d+)", text)
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    q = re.search(r"batch:\s*(\d+)", text)
     if not (h and d and b) or h.group(1) != engine_hash() or int(d.group(1)) != delta:
+        return None
+    if (int(q.group(1)) if q else 1) != batch:
         return None
     return float(b.group(1))
 
@@ -465,9 +474,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=4096)
-    ap.add_argument("--delta", type=int, default=512,
-                    help="bucket width of the headline (512: the fastest of the 2^8..2^14 sweep on this graph, "
-                         "which every run repeats); 0 = run at the sweep's fastest")
+    ap.add_argument("--delta", type=int, default=1024,
+                    help="bucket width of the headline's batched launch (1024: the fastest of its 2^8..2^14 "
+                         "sweep on this graph, which every run repeats); 0 = run at the sweep's fastest")
+    ap.add_argument("--serial-delta", type=int, default=512,
+                    help="bucket width of the one-query-per-launch legs (512: the fastest of their sweep); "
+                         "0 = the sweep's fastest")
     ap.add_argument("--sources", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and parity leg")
     ap.add_argument("--no-variants", action="store_true", help="skip the unfused / host-driven legs")
@@ -535,20 +547,43 @@ def main() -> int:
     # headline without them
     TB = og.OG_FLAG_TIMING | og.OG_FLAG_DEGREE_BINS
 
-    # the configuration sweeps Delta over 2^8..2^14: engine time per query,
-    # fused with the headline's load balancing, on the first two sources
+    # The configuration sweeps Delta over 2^8..2^14, for both ways of running
+    # the workload, fused with the headline's load balancing: one query per
+    # launch (engine ms per query, first two sources) and all sources in one
+    # batched launch (engine ms per launch).
     sweep = {}
     for dlt in SWEEP:
         sch = og.Schedule(delta=dlt, update=og.OG_EAGER_WITH_FUSION, flags=TB)
         step(0, sch)
         sweep[dlt] = round(float(np.mean([step(i, sch)["engine_ms"] for i in range(min(2, len(srcs)))])), 3)
-    print(f"[bench] delta sweep (engine ms): {sweep}", file=sys.stderr, flush=True)
+    print(f"[bench] serial delta sweep (engine ms per query): {sweep}", file=sys.stderr, flush=True)
+    if args.serial_delta <= 0:
+        args.serial_delta = min(sweep, key=sweep.get)
+
+    # The timed step: every source of the workload in one og_sssp_batch
+    # launch (distances and canonical predecessors of all of them).
+    hws = og.Workspace(dev)
+    hdist = torch.empty((len(srcs), g.n), dtype=torch.int32, device=dev)
+    hpred = torch.empty((len(srcs), g.n), dtype=torch.int32, device=dev)
+
+    def bstep(sched):
+        _, _, st = og.sssp_batch(dg, srcs, sched, ws=hws, out_dist=hdist, out_pred=hpred)
+        return st
+
+    bsweep = {}
+    for dlt in SWEEP:
+        sch = og.Schedule(delta=dlt, update=og.OG_EAGER_WITH_FUSION, flags=TB)
+        bstep(sch)
+        bsweep[dlt] = round(bstep(sch)["engine_ms"], 3)
+    print(f"[bench] batched delta sweep (engine ms per launch of {len(srcs)}): {bsweep}", file=sys.stderr,
+          flush=True)
     if args.delta <= 0:
-        args.delta = min(sweep, key=sweep.get)
-    fused = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=TB)
+        args.delta = min(bsweep, key=bsweep.get)
+    fused = og.Schedule(delta=args.serial_delta, update=og.OG_EAGER_WITH_FUSION, flags=TB)
+    head = og.Schedule(delta=args.delta, update=og.OG_EAGER_WITH_FUSION, flags=TB)
 
     for i in range(args.warmup):
-        step(i, fused)
+        bstep(head)
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
@@ -556,7 +591,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        stats.append(step(i, fused))
+        stats.append(bstep(head))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     print(f"[bench] timed {args.steps} steps in {wall:.3f}s", file=sys.stderr, flush=True)
@@ -570,10 +605,34 @@ def main() -> int:
     # algorithmic bytes of one bucket-engine launch: 12 B per reached edge
     # (col + w + the dist word read by the atomic minimum) and 28 B per
     # reached vertex (row_ptr pair, queue push and pop of an 8-byte entry,
-    # final dist write)
+    # final dist write), summed over the launch's queries
     alg_bytes = (12.0 * reached_e + 28.0 * reached_v) / len(stats)
     achieved = alg_bytes / (engine_ms * 1e-3) / 1e9
-    traffic = read_traffic(args.delta)
+    traffic = read_traffic(args.delta, len(srcs))
+
+    # the same sources one query per launch (the serial figure the batched
+    # step is compared with), with the same load balancing
+    serial_st = [step(i, fused) for i in range(len(srcs))]  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    serial_st = [step(i, fused) for i in range(len(srcs))]
+    torch.cuda.synchronize()
+    serial_wall = time.perf_counter() - t
+    serial_fig = {
+        "delta": args.serial_delta,
+        "ms_per_query": round(serial_wall / len(srcs) * 1e3, 3),
+        "engine_ms": round(float(np.mean([s_["engine_ms"] for s_ in serial_st])), 3),
+        "gteps": round(sum(s_["reached_edges"] for s_ in serial_st) / serial_wall / 1e9, 4),
+        "rounds": int(np.mean([s_["rounds"] for s_ in serial_st])),
+        "chain": int(np.mean([s_["chain"] for s_ in serial_st])),
+        "alg_roofline_frac": round(float(np.mean([(12.0 * s_["reached_edges"] + 28.0 * s_["reached_vertices"])
+                                                  / (s_["engine_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                                  for s_ in serial_st])), 5),
+        "traffic_bytes_per_launch": read_traffic(args.serial_delta, 1),
+        "queries": len(srcs),
+    }
+    print(f"[bench] serial: {serial_fig['ms_per_query']:.2f} ms/query, {serial_fig['gteps']:.3f} GTEPS",
+          file=sys.stderr, flush=True)
 
     variants = {}
     if not args.no_variants:
@@ -598,7 +657,7 @@ def main() -> int:
             print(f"[bench] variant {name}: {ms:.2f} ms/query", file=sys.stderr, flush=True)
             return variants[name]
 
-        d = args.delta
+        d = args.serial_delta
         for name, upd, eng, fl in (
                 ("fused", og.OG_EAGER_WITH_FUSION, og.OG_ENGINE_PERSISTENT, TB),
                 ("unfused", og.OG_EAGER_NO_FUSION, og.OG_ENGINE_PERSISTENT, TB),
@@ -698,8 +757,13 @@ def main() -> int:
             refs = list(ex.map(lambda s_: orc.sssp(g, s_), srcs))
         par_s = time.perf_counter() - t
         par_e = sum(reached_edges(d) for d, _ in refs)
+        # the headline's batched launch and the serial schedule, every source
         parity = True
+        bstep(head)
+        torch.cuda.synchronize()
         for i, (d_ref, p_ref) in enumerate(refs):
+            parity &= bool(np.array_equal(hdist[i].cpu().numpy(), d_ref)) and bool(
+                np.array_equal(hpred[i].cpu().numpy(), p_ref))
             step(i, fused)
             torch.cuda.synchronize()
             parity &= bool(np.array_equal(dist.cpu().numpy(), d_ref)) and bool(
@@ -728,7 +792,11 @@ def main() -> int:
         "config": {
             "workload": f"SSSP on road-like {args.side}x{args.side} grid (p_keep 0.75, 0.1% long-range "
                         f"<=64 steps, {ROAD_WEIGHTS}, seed 0), {len(srcs)} sources (seed 1)",
-            "n": g.n, "m": g.m, "delta": args.delta, "delta_sweep_engine_ms": sweep,
+            "step": f"all {len(srcs)} sources in one og_sssp_batch launch (dist + pred of each); the same "
+                    f"sources one query per launch are under 'serial'",
+            "queries_per_launch": len(srcs),
+            "n": g.n, "m": g.m, "delta": args.delta, "delta_sweep_engine_ms": bsweep,
+            "serial_delta_sweep_engine_ms": sweep,
             "update": "eager_with_fusion", "engine": "persistent",
             "load_balance": "degree bins (lane <= 4 edges, wavefront <= 64, workgroup above)",
             "outputs": "dist + canonical pred",
@@ -750,12 +818,15 @@ def main() -> int:
         },
         "phases_ms": {"init": round(init_ms, 3), "engine": round(engine_ms, 3), "pred": round(pred_ms, 3)},
         "rounds": int(np.mean([s["rounds"] for s in stats])),
-        "relaxations_per_query": int(np.mean([s["relaxations"] for s in stats])),
-        "improvements_per_query": int(np.mean([s["improvements"] for s in stats])),
-        "pushes_per_query": int(np.mean([s["pushes_local"] + s["pushes_global"] for s in stats])),
+        "chain": int(np.mean([s["chain"] for s in stats])),
+        "relaxations_per_query": int(np.mean([s["relaxations"] for s in stats]) / len(srcs)),
+        "improvements_per_query": int(np.mean([s["improvements"] for s in stats]) / len(srcs)),
+        "pushes_per_query": int(np.mean([s["pushes_local"] + s["pushes_global"] for s in stats]) / len(srcs)),
         # global-queue entries in use at once (whole 4,096-entry chunks) and the workspace
         "queue_pool_peak_entries": int(max(s["pool_needed"] for s in stats)),
-        "workspace_bytes": int(og.workspace_bytes(dg, fused)),
+        "workspace_bytes": int(og.workspace_bytes(dg, head, batch=len(srcs))),
+        "serial": serial_fig,
+        "batched_vs_serial": round(serial_fig["ms_per_query"] / (wall / args.steps * 1e3 / len(srcs)), 2),
         "variants": variants,
         "cpu_baseline": cpu,
         "parity_on_cpu_sample": parity,
@@ -763,7 +834,7 @@ def main() -> int:
     print(json.dumps(line), flush=True)
     # orderly teardown before interpreter exit (profilers attached to the
     # process finalise in exit handlers)
-    del dg, dist, pred, ws
+    del dg, dist, pred, ws, hdist, hpred, hws
     og.release()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()

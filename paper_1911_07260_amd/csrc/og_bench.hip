@@ -16,6 +16,8 @@
 //                                  split copy across the calls)
 //            [--blocks [--block-size N]]   (LDS-resident vertex blocks, the
 //                                  blocked copy kept across the calls)
+//            [--batch N]   (each step: one og_sssp_batch call over the first N
+//                           sources)
 //            [--copy-calibration]
 //
 // --copy-calibration instead runs a plain copy kernel over 1 GiB three
@@ -83,7 +85,7 @@ int main(int argc, char** argv) {
   bool rmat = false, kcore = false;
   uint32_t direction = 0;
   bool bins = false, split = false, keep = false, blocks = false;
-  int block_size = 0;
+  int block_size = 0, batch = 0;
   for (int i = 1; i < argc; ++i) {
     auto next = [&](void) -> const char* {
       if (i + 1 >= argc) { std::fprintf(stderr, "missing value for %s\n", argv[i]); std::exit(2); }
@@ -117,10 +119,16 @@ int main(int argc, char** argv) {
     else if (!std::strcmp(argv[i], "--keep")) keep = true;
     else if (!std::strcmp(argv[i], "--blocks")) blocks = true;
     else if (!std::strcmp(argv[i], "--block-size")) block_size = std::atoi(next());
+    else if (!std::strcmp(argv[i], "--batch")) batch = std::atoi(next());
     else if (!std::strcmp(argv[i], "--copy-calibration")) return copy_calibration();
     else { std::fprintf(stderr, "unknown argument %s\n", argv[i]); return 2; }
   }
 
+  if (batch < 0 || (batch > 0 && kcore)) {
+    std::fprintf(stderr, "--batch needs N >= 1 and no --kcore\n");
+    return 2;
+  }
+  if (batch > nsrc) nsrc = batch;
   // road: as graphgen.road(side, seed=0); rmat: as graphgen.rmat(scale, 16, seed=0), w in [1, 1000)
   void* h = rmat ? gg_rmat(scale, 16, 0.57, 0.19, 0.19, 1, 1000, 0) : gg_road(side, 0.75, 0.001, 64, 0);
   if (!h) { std::fprintf(stderr, "graph generation failed\n"); return 1; }
@@ -144,8 +152,9 @@ int main(int argc, char** argv) {
   CHECK(hipMalloc(&d_rp, sizeof(int64_t) * ((size_t)n + 1)));
   CHECK(hipMalloc(&d_col, sizeof(int32_t) * (size_t)m));
   CHECK(hipMalloc(&d_w, sizeof(int32_t) * (size_t)m));
-  CHECK(hipMalloc(&d_dist, sizeof(int32_t) * (size_t)n));
-  CHECK(hipMalloc(&d_pred, sizeof(int32_t) * (size_t)n));
+  const size_t nout = (size_t)n * (size_t)(batch > 0 ? batch : 1);
+  CHECK(hipMalloc(&d_dist, sizeof(int32_t) * nout));
+  CHECK(hipMalloc(&d_pred, sizeof(int32_t) * nout));
   CHECK(hipMemcpy(d_rp, row_ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice));
   CHECK(hipMemcpy(d_col, col.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice));
   CHECK(hipMemcpy(d_w, w.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice));
@@ -160,7 +169,9 @@ int main(int argc, char** argv) {
             (split && keep ? OG_FLAG_KEEP_SPLIT : 0u) | (blocks ? OG_FLAG_VERTEX_BLOCKS | OG_FLAG_KEEP_BLOCKS : 0u);
   if (block_size > 0) s.block_size = block_size;
   if (window > 0) s.window_buckets = window;
-  const size_t wsb = kcore ? og_workspace_bytes_kcore(&g, &s) : og_workspace_bytes(&g, &s);
+  const size_t wsb = kcore ? og_workspace_bytes_kcore(&g, &s)
+                    : batch > 0 ? og_workspace_bytes_batch(&g, &s, batch)
+                                : og_workspace_bytes(&g, &s);
   void* ws = nullptr;
   CHECK(hipMalloc(&ws, wsb));
   hipStream_t stream;
@@ -169,10 +180,12 @@ int main(int argc, char** argv) {
   double eng = 0, pred = 0, tot_e = 0, rounds = 0;
   for (int i = 0; i < warmup + steps; ++i) {
     og_stats st;
-    const og_status rc = kcore ? og_kcore(&g, &s, d_dist, ws, wsb, &st, stream)
-                               : og_sssp(&g, srcs[i % nsrc], &s, d_dist, d_pred, ws, wsb, &st, stream);
+    const og_status rc = kcore       ? og_kcore(&g, &s, d_dist, ws, wsb, &st, stream)
+                         : batch > 0 ? og_sssp_batch(&g, srcs.data(), batch, &s, d_dist, d_pred, ws, wsb, &st, stream)
+                                     : og_sssp(&g, srcs[i % nsrc], &s, d_dist, d_pred, ws, wsb, &st, stream);
     if (rc != OG_OK) {
-      std::fprintf(stderr, "%s failed: %s\n", kcore ? "og_kcore" : "og_sssp", og_status_string(rc));
+      std::fprintf(stderr, "%s failed: %s\n", kcore ? "og_kcore" : batch > 0 ? "og_sssp_batch" : "og_sssp",
+                   og_status_string(rc));
       return 1;
     }
     if (i >= warmup) {
@@ -180,14 +193,18 @@ int main(int argc, char** argv) {
       pred += st.pred_ms;
       tot_e += (double)st.reached_edges;
       rounds += (double)st.rounds;
-      std::fprintf(stderr, "step %d src %d: engine %.3f ms pred %.3f ms rounds %lld\n", i - warmup,
-                   srcs[i % nsrc], st.engine_ms, st.pred_ms, (long long)st.rounds);
+      if (batch > 0)
+        std::fprintf(stderr, "step %d batch of %d: engine %.3f ms pred %.3f ms rounds %lld\n", i - warmup, batch,
+                     st.engine_ms, st.pred_ms, (long long)st.rounds);
+      else
+        std::fprintf(stderr, "step %d src %d: engine %.3f ms pred %.3f ms rounds %lld\n", i - warmup,
+                     srcs[i % nsrc], st.engine_ms, st.pred_ms, (long long)st.rounds);
     }
   }
-  std::printf("{\"graph\": \"%s\", \"call\": \"%s\", \"n\": %d, \"m\": %lld, \"delta\": %d, \"update\": %d, "
+  std::printf("{\"graph\": \"%s\", \"call\": \"%s\", \"batch\": %d, \"n\": %d, \"m\": %lld, \"delta\": %d, \"update\": %d, "
               "\"engine\": %d, \"direction\": %u, \"steps\": %d, \"engine_ms\": %.4f, \"pred_ms\": %.4f, \"rounds\": %.1f, "
               "\"reached_edges\": %.0f}\n",
-              rmat ? "rmat" : "road", kcore ? "og_kcore" : "og_sssp", n, (long long)m, delta, update, engine, direction, steps,
+              rmat ? "rmat" : "road", kcore ? "og_kcore" : batch > 0 ? "og_sssp_batch" : "og_sssp", batch, n, (long long)m, delta, update, engine, direction, steps,
               eng / steps, pred / steps, rounds / steps, tot_e / steps);
   if (og_release() != OG_OK) {
     std::fprintf(stderr, "og_release failed\n");

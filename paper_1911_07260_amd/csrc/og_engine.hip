@@ -861,10 +861,10 @@ __device__ void process_batch(const Args& a, Smem& s, Counters& c, int4 ent, boo
   const int nb = s.nb;
   const unsigned cur = s.cur;
   // A plain load of dist[u] skips atomics that cannot succeed.  It costs a
-  // dependent round trip, so a small locally chased batch (latency-bound,
-  // one pass over its edges) goes straight to the atomic; larger batches
-  // (throughput-bound) filter.
-  const bool prefilter = !from_lds || total > kBlock;
+  // dependent round trip, so a small locally chased batch of one query
+  // (latency-bound, one pass over its edges) goes straight to the atomic;
+  // larger batches and batched launches (throughput-bound) filter.
+  const bool prefilter = !from_lds || total > kBlock || a.reps > 1;
   if constexpr (W::kWide) {
     if (total > kBlock) {
       relax_wide<W>(a, s, c, from_lds, total, nb, cur);
@@ -1025,7 +1025,12 @@ __device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 e
   const int lane_max = a.bin_thread < kBinLane ? a.bin_thread : kBinLane;
   const bool in_lane = deg > 0 && deg <= lane_max;
   const bool in_wave = deg > lane_max && deg <= a.bin_wave;
-  const bool prefilter = !from_lds;
+  // The plain-load filter (an atomic only where dist[u] still looks larger)
+  // is used for global entries, and for every entry of a batched launch:
+  // with several queries in flight the device-scope atomics queue at the
+  // memory side and dropping the hopeless ones pays; for one query the
+  // filter's extra dependent load only lengthens the ring's chain.
+  const bool prefilter = !from_lds || a.reps > 1;
   // Ring entries get their staleness check per edge: the vertex's current
   // distance is loaded together with the edge (global entries were checked
   // above).
@@ -1126,7 +1131,8 @@ __device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 e
       const int wk = a.w[edge];
       const int dn = from_lds ? a.dist[s.bv[lo]] : dsrc;
       u = ubk + s.bvo[lo];
-      has = relax_edge<W>(a, s, c, ubk, wk, dsrc, dn, u, !from_lds || total > kBlock, &nd, &b, &r0, &rdeg);
+      has = relax_edge<W>(a, s, c, ubk, wk, dsrc, dn, u, !from_lds || total > kBlock || a.reps > 1, &nd, &b,
+                          &r0, &rdeg);
     }
     finish_edges(a, s, c, has, u, nd, b, r0, rdeg);
   }

@@ -13,6 +13,12 @@ def test_traffic_matches_engine_and_delta(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.read_traffic(512) == 12345.0
     assert bench.read_traffic(1024) is None
+    fb = tmp_path / "traffic_b.txt"
+    fb.write_text("traffic_bytes_per_launch: 777\ndelta: 1024\nbatch: 8\nengine_code_sha256_16: "
+                  + bench.engine_hash() + "\n")
+    monkeypatch.setattr(bench, "BATCH_TRAFFIC_FILE", str(fb))
+    assert bench.read_traffic(1024, 8) == 777.0
+    assert bench.read_traffic(1024, 16) is None and bench.read_traffic(512, 8) is None
     f.write_text("traffic_bytes_per_launch: 12345\ndelta: 512\nengine_code_sha256_16: 0000000000000000\n")
     assert bench.read_traffic(512) is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
@@ -30,9 +36,11 @@ def test_engine_hash_ignores_comments_only():
 
 
 def test_committed_profile_is_current():
-    """The committed traffic summary was taken on the committed engine at
-    the headline Delta (512)."""
-    assert os.path.exists(bench.TRAFFIC_FILE)
+    """The committed traffic summaries were taken on the committed engine:
+    the headline's batched launch of 8 queries at Delta 1024, and one query
+    per launch at Delta 512."""
+    assert os.path.exists(bench.TRAFFIC_FILE) and os.path.exists(bench.BATCH_TRAFFIC_FILE)
+    assert bench.read_traffic(1024, 8) is not None
     assert bench.read_traffic(512) is not None
 
 
@@ -41,6 +49,8 @@ def test_kernel_profiles_are_current():
     current engine were taken on it (a code change without retaking them
     fails here); the two older counter sets say which code they were taken on."""
     current = ["k_persistent_road4096_traffic.txt", "kernels_road4096_d512_fused.txt",
+               "k_persistent_road4096_batch8_traffic.txt", "kernels_road4096_batch8_d1024.txt",
+               "kernels_road4096_blocks_d2048.txt", "k_persistent_road4096_bins_counters.txt",
                "kernels_kcore_rmat24_lazy.txt", "kernels_sssp_rmat24_d32_unfused.txt",
                "kernels_sssp_rmat24_split_d64_kept_counters.txt"]
     h = bench.engine_hash()
@@ -48,7 +58,7 @@ def test_kernel_profiles_are_current():
     for name in current:
         text = open(os.path.join(pdir, name)).read()
         assert "engine_code_sha256_16: " + h in text, name
-    for name in ("k_persistent_road4096_stalls.txt", "k_persistent_road4096_bins_counters.txt"):
+    for name in ("k_persistent_road4096_stalls.txt",):
         assert "engine_code_sha256_16: " in open(os.path.join(pdir, name)).read(), name
 
 
