@@ -235,6 +235,17 @@ typedef struct og_schedule {
                                when a queue has been consumed (0 = twice
                                queue_capacity plus one chunk per queue); an
                                empty pool ends the call with OG_ERR_WORKSPACE */
+  int32_t teams;            /* batched calls of the eager push engine: teams
+                               of workgroups (workgroup b in team b mod
+                               teams), each with its own queues and the
+                               queries q with q mod teams = team; the
+                               hardware deals consecutive workgroups to the 8
+                               XCDs in turn, so a team's work stays in the
+                               L2s of its XCDs.  0 = 1 below 8 queries, 2
+                               from 8, 4 from 32; at most 8, one per query
+                               and one per workgroup.  Other calls,
+                               OG_LAZY_UPDATE and the split, pull and block
+                               variants run one team                          */
 } og_schedule;
 
 /* Per-call counters (host struct). */

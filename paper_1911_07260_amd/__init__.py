@@ -73,6 +73,7 @@ class Schedule:
     bin_wave: int = 0
     block_size: int = 0
     queue_pool: int = 0
+    teams: int = 0
 
     @property
     def fused(self) -> bool:

@@ -78,6 +78,7 @@ class OgSchedule(ctypes.Structure):
         ("bin_wave", ctypes.c_int32),
         ("block_size", ctypes.c_int32),
         ("queue_pool", ctypes.c_int64),
+        ("teams", ctypes.c_int32),
     ]
 
 

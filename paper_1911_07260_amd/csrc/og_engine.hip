@@ -82,7 +82,15 @@ constexpr int kMaxGroups = kMaxWg / kGroup;
 constexpr int kFlags = 64;  // release flags, one per 128-byte line
 constexpr int kMaxQueries = 1024;    // queries in one launch
 constexpr int kMaxBatch = 1 << 20;  // queries in one batch call (in launches of at most kMaxQueries)
-constexpr size_t kCtlBytes = 65536;
+constexpr size_t kCtlBytes = 131072;
+// A batched launch splits its workgroups into teams: workgroup b serves team
+// b % teams, which owns the queries q with q % teams == team and a set of
+// bucket lists of its own.  The hardware deals consecutive workgroups to the
+// XCDs in turn, so with 8 teams each XCD's L2 holds the working set of its
+// own queries only.  Every vertex a team files belongs to one of its queries
+// (edges stay within a query's copy of the graph), so a team's lists, LDS
+// rings and pushes never mix teams.
+constexpr int kMaxTeams = 8;
 // The global bucket lists (K window slots, 2 spill lists, 2 far lists) draw
 // fixed-size chunks from one shared pool: list L's position p lives in the
 // chunk its table names for p / kChunk.  A list's chunks go back to the
@@ -160,7 +168,6 @@ struct alignas(128) Control {
   unsigned cur;       // current bucket
   unsigned in_kind;   // round input: window slot / spill list / far list
   unsigned in_index;
-  unsigned in_count;
   unsigned done;
   unsigned spill_out;  // spill list receiving current-bucket pushes
   unsigned far_in;     // far list holding pending overflow entries
@@ -174,18 +181,25 @@ struct alignas(128) Control {
   unsigned pull;     // direction of this round: 1 = dense pull (pull instantiations)
 };
 
-// Device-side control block at the start of the workspace.
-struct Ctl {
-  Control c;
-  Word status;
-  Word in_head;  // dynamic chunk cursor into a large round input
-  Word bar_root;
-  Word bar_grp[kMaxGroups];
-  Word flag[kFlags];  // release flags: the round number now allowed to start
+// A team's bucket lists: the fill of each, the smallest bucket filed in
+// each far list, and the team's share of the round input.
+struct TeamQ {
+  Word in_count;  // entries of the team's round input list
+  Word in_head;   // dynamic chunk cursor into a large round input
   Word win_tail[kKmax];
   Word spill_tail[2];
   Word far_tail[2];
   Word far_min[2];
+};
+
+// Device-side control block at the start of the workspace.
+struct Ctl {
+  Control c;
+  Word status;
+  Word bar_root;
+  Word bar_grp[kMaxGroups];
+  Word flag[kFlags];  // release flags: the round number now allowed to start
+  TeamQ tq[kMaxTeams];
   Word round_max_batches;  // most batches one workgroup ran in the current round
   Word buf_tail;           // lazy update: entries in the change buffer
   Word64 need;
@@ -223,9 +237,10 @@ struct Args {
   unsigned threshold;
   unsigned max_rounds;
   int nwg;
+  int teams;  // workgroup teams (1, or up to kMaxTeams in a batched launch)
   Ctl* ctl;
   int2* pool;         // [pool_chunks * kChunk] entries of every global list
-  int* ctab;          // [(K + 4) * tchunks] chunk of each list position / kChunk
+  int* ctab;          // [teams * (K + 4) * tchunks] chunk of each list position / kChunk
   int* fstack;        // [pool_chunks] free chunks (the bottom free_top entries)
   unsigned pool_chunks;
   unsigned tchunks;   // table entries per list: ceil(cap / kChunk)
@@ -269,8 +284,11 @@ struct Args {
   int nb;
 };
 
+// Per-thread event counts, 32 bits each (registers are what limits the
+// persistent kernels' occupancy); round_barrier adds them to the 64-bit
+// totals before any can pass 2^31.
 struct Counters {
-  unsigned long long relax = 0, improve = 0, push_local = 0, push_global = 0, far = 0, batches = 0;
+  unsigned relax = 0, improve = 0, push_local = 0, push_global = 0, far = 0, batches = 0;
   unsigned round_batches = 0;
 };
 
@@ -291,6 +309,7 @@ struct Smem {
   // snapshot of the control block for this round
   unsigned cur, in_count, win_hi, round, epoch, far_stamp;
   int in_kind, in_index, done, spill_out, far_out;
+  int team, team_rank, team_size;  // this workgroup's team, its index in it, the team's workgroups
   int hout;       // light/heavy split
   unsigned hgen;  // light/heavy split
   int pull;       // this round pulls
@@ -352,6 +371,10 @@ struct IntW {
   static constexpr bool kPull = false;
   static constexpr bool kBin = false;
   static constexpr bool kBlocks = false;
+  // wavefronts per SIMD the persistent kernel is compiled for: 6 fits its
+  // 25.7 KB of LDS per workgroup and keeps a latency-bound road chain fed
+  // (1 = as many as its registers allow)
+  static constexpr int kMinWaves = 6;
   // nd = d + w; false (and a status) for a negative weight or a sum that
   // reaches INT32_MAX
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
@@ -382,6 +405,7 @@ struct IntW {
 struct FloatW {
   static constexpr int kInfBits = 0x7f800000;  // +inf
   static constexpr bool kSplit = false;
+  static constexpr int kMinWaves = 1;
   static constexpr bool kWide = true;
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
@@ -432,6 +456,7 @@ struct CoreW : IntW {
 struct SplitW : IntW {
   static constexpr bool kSplit = true;
   static constexpr bool kWide = true;
+  static constexpr int kMinWaves = 1;
   __device__ static bool light(const Args& a, int wraw) { return wraw < (int)a.delta; }
 };
 
@@ -444,9 +469,11 @@ struct SplitW : IntW {
 // engines.
 struct PullW : IntW {
   static constexpr bool kPull = true;
+  static constexpr int kMinWaves = 5;
 };
 struct CorePullW : CoreW {
   static constexpr bool kPull = true;
+  static constexpr int kMinWaves = 5;
 };
 
 // Degree-binned load balancing: within a batch, a vertex of at most
@@ -470,9 +497,10 @@ struct BlockW : IntW {
   static constexpr bool kBlocks = true;
 };
 
-// List ids: window slots 0 .. K-1, spill lists K, K+1, far lists K+2, K+3.
-__device__ __forceinline__ int list_of(const Args& a, int kind, int index) {
-  return kind == kInWin ? index : (kind == kInSpill ? a.K + index : a.K + 2 + index);
+// List ids: team t's window slots t(K+4) + 0 .. K-1, spill lists + K, K+1,
+// far lists + K+2, K+3.
+__device__ __forceinline__ int list_of(const Args& a, int team, int kind, int index) {
+  return team * (a.K + 4) + (kind == kInWin ? index : (kind == kInSpill ? a.K + index : a.K + 2 + index));
 }
 __device__ __forceinline__ unsigned* chunk_slot(const Args& a, int list, unsigned pos) {
   return reinterpret_cast<unsigned*>(a.ctab) + (size_t)list * a.tchunks + (pos >> kChunkLog);
@@ -547,6 +575,10 @@ __device__ void wave_push_global(const Args& a, const S& s, Counters& c, bool ha
                                  unsigned b) {
   Ctl* ctl = a.ctl;
   const int K = a.K;
+  if (a.teams > 1 && has && query_of(a, v) % a.teams != s.team) {  // another team's vertex: a library bug
+    set_status(ctl, OG_ERR_INTERNAL);
+    has = false;
+  }
   for (;;) {
     const unsigned long long m = __ballot(has);
     if (m == 0) break;
@@ -554,17 +586,18 @@ __device__ void wave_push_global(const Args& a, const S& s, Counters& c, bool ha
     const int t = __shfl(tgt, leader);
     const bool mine = has && tgt == t;
     const unsigned long long mm = __ballot(mine);
+    TeamQ& q = ctl->tq[s.team];
     unsigned* tail;
     int list;
     if (t < K) {
-      tail = &ctl->win_tail[t].v;
-      list = t;
+      tail = &q.win_tail[t].v;
+      list = list_of(a, s.team, kInWin, t);
     } else if (t == K) {
-      tail = &ctl->spill_tail[s.spill_out].v;
-      list = K + s.spill_out;
+      tail = &q.spill_tail[s.spill_out].v;
+      list = list_of(a, s.team, kInSpill, s.spill_out);
     } else {
-      tail = &ctl->far_tail[s.far_out].v;
-      list = K + 2 + s.far_out;
+      tail = &q.far_tail[s.far_out].v;
+      list = list_of(a, s.team, kInFar, s.far_out);
     }
     unsigned base = 0;
     if ((int)lane_id() == leader) base = atomicAdd(tail, (unsigned)__popcll(mm));
@@ -576,7 +609,7 @@ __device__ void wave_push_global(const Args& a, const S& s, Counters& c, bool ha
           c.push_global++;
           if (t == K + 1) {
             c.far++;
-            atomicMin(&ctl->far_min[s.far_out].v, b);
+            atomicMin(&q.far_min[s.far_out].v, b);
           }
         }
         has = false;
@@ -1146,7 +1179,7 @@ __device__ void process_batch_binned(const Args& a, Smem& s, Counters& c, int4 e
 // kPeeled, above every generation) is never filed there again.
 __device__ void route_core(const Args& a, Smem& s, Counters& c, bool has, int u, int p, int r0, int deg) {
   if (has && (unsigned)p >= s.win_hi) {
-    atomicMin(&a.ctl->far_min[s.far_out].v, (unsigned)p);
+    atomicMin(&a.ctl->tq[s.team].far_min[s.far_out].v, (unsigned)p);
     if (atomicMax(&a.mark[u], (int)s.far_stamp) >= (int)s.far_stamp) has = false;
   }
   route_push(a, s, c, has, u, p, (unsigned)p, r0, deg);
@@ -1293,10 +1326,10 @@ __device__ void run_flush(const Args& a, Smem& s, Counters& c) {
 __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
   const unsigned h = s.lq_head, cnt = s.lq_tail - s.lq_head;
-  if (tid == 0) s.gbase = atomicAdd(&a.ctl->spill_tail[s.spill_out].v, cnt);
+  if (tid == 0) s.gbase = atomicAdd(&a.ctl->tq[s.team].spill_tail[s.spill_out].v, cnt);
   __syncthreads();
   const unsigned gb = s.gbase;
-  const int list = a.K + s.spill_out;
+  const int list = list_of(a, s.team, kInSpill, s.spill_out);
   for (unsigned i0 = 0; i0 < cnt; i0 += kBlock) {
     const unsigned i = i0 + tid;
     bool spill_far = false;
@@ -1316,6 +1349,33 @@ __device__ void publish_local(const Args& a, Smem& s, Counters& c) {
   if (tid == 0) s.lq_head = s.lq_tail = 0;
 }
 
+// Thread 0 takes the workgroup's next share of its team's round input:
+// an input that fits in one batch per workgroup of the team is split
+// statically (the team's b-th workgroup takes the b-th slice, no atomics);
+// a larger one is handed out in kBlock chunks through the team's cursor.
+// Sets s.mode = 2 with s.nb entries from s.gbase, or s.exhausted.
+template <class S>
+__device__ void take_input(const Args& a, S& s) {
+  const unsigned count = s.in_count, tsize = (unsigned)s.team_size;
+  const bool fixed = count <= tsize * (unsigned)kBlock;
+  const unsigned per = fixed ? (count + tsize - 1) / tsize : (unsigned)kBlock;
+  unsigned base;
+  if (fixed) {
+    base = (unsigned)s.team_rank * per;
+    s.exhausted = 1;
+  } else {
+    base = atomicAdd(&a.ctl->tq[s.team].in_head.v, (unsigned)kBlock);
+  }
+  if (base < count) {
+    s.mode = 2;
+    const unsigned left = count - base;
+    s.nb = (int)(left < per ? left : per);
+    s.gbase = base;
+  } else {
+    s.exhausted = 1;
+  }
+}
+
 // One round: the round input list, then (fused) the local current bucket.
 // A round input that fits in one batch per workgroup is split statically
 // (workgroup b takes the b-th slice, no atomics); a larger one is handed
@@ -1325,10 +1385,6 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
   // the round input: a heavy list (light/heavy split) or a pooled list
   const int2* hin = W::kSplit && s.in_kind == kInHeavy ? a.heavy + (size_t)s.in_index * a.hcap : nullptr;
-  const int in_list = list_of(a, s.in_kind, s.in_index);
-  const unsigned count = s.in_count;
-  const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
-  const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
   if (tid == 0) {
     s.lq_head = s.lq_tail = 0;
     s.exhausted = 0;
@@ -1348,21 +1404,7 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
         s.bhead = s.lq_head;
         s.lq_head += (unsigned)s.nb;  // entries are read before any push of this batch
       } else if (!s.exhausted) {
-        unsigned base;
-        if (fixed) {
-          base = (unsigned)blockIdx.x * per;
-          s.exhausted = 1;
-        } else {
-          base = atomicAdd(&a.ctl->in_head.v, (unsigned)kBlock);
-        }
-        if (base < count) {
-          s.mode = 2;
-          const unsigned left = count - base;
-          s.nb = (int)(left < per ? left : per);
-          s.gbase = base;
-        } else {
-          s.exhausted = 1;
-        }
+        take_input(a, s);
       }
     }
     __syncthreads();
@@ -1382,7 +1424,7 @@ __device__ void run_round(const Args& a, Smem& s, Counters& c) {
         ent = s.lq[(s.bhead + tid) & (kLq - 1)];
       } else {
         const unsigned pos = s.gbase + (unsigned)tid;
-        const int2 e = hin ? ld_entry(hin, pos) : load_at(a, in_list, pos);
+        const int2 e = hin ? ld_entry(hin, pos) : load_at(a, list_of(a, s.team, s.in_kind, s.in_index), pos);
         ent = make_int4(e.x, e.y, 0, 0);
       }
     }
@@ -1417,11 +1459,12 @@ __device__ __forceinline__ void mark_peeled(const Args& a, int v) {
 // in the bitmap.
 template <class W>
 __device__ void run_mark(const Args& a, Smem& s, Counters& c) {
-  const int in_list = list_of(a, s.in_kind, s.in_index);
+  const int in_list = list_of(a, s.team, s.in_kind, s.in_index);
   const unsigned count = s.in_count;
   const unsigned cur = s.cur;
   const int stamp = pull_stamp(s);
-  for (unsigned base = blockIdx.x * (unsigned)kBlock; base < count; base += (unsigned)a.nwg * kBlock) {
+  for (unsigned base = (unsigned)s.team_rank * (unsigned)kBlock; base < count;
+       base += (unsigned)s.team_size * kBlock) {
     const unsigned i = base + threadIdx.x;
     bool later = false;
     int v = 0, d = 0;
@@ -1595,7 +1638,7 @@ __device__ void run_pull(const Args& a, Smem& s, Counters& c) {
   const int stamp = pull_stamp(s);
   for (;;) {
     __syncthreads();  // the previous item's shared state is no longer read
-    if (tid == 0) s.gbase = atomicAdd(&a.ctl->in_head.v, 1u);
+    if (tid == 0) s.gbase = atomicAdd(&a.ctl->tq[s.team].in_head.v, 1u);
     __syncthreads();
     const unsigned item = s.gbase;
     if (item >= nsl + nvb) break;
@@ -1685,10 +1728,6 @@ __device__ void run_pull(const Args& a, Smem& s, Counters& c) {
 template <class W>
 __device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
   const int tid = threadIdx.x;
-  const int in_list = list_of(a, s.in_kind, s.in_index);
-  const unsigned count = s.in_count;
-  const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
-  const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
   if (tid == 0) {
     s.lq_head = s.lq_tail = 0;
     s.exhausted = 0;
@@ -1718,21 +1757,7 @@ __device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
           s.bhead = s.lq_head;
           s.lq_head += (unsigned)s.nb;
         } else if (!s.exhausted) {
-          unsigned base;
-          if (fixed) {
-            base = (unsigned)blockIdx.x * per;
-            s.exhausted = 1;
-          } else {
-            base = atomicAdd(&a.ctl->in_head.v, (unsigned)kBlock);
-          }
-          if (base < count) {
-            s.mode = 2;
-            const unsigned left = count - base;
-            s.nb = (int)(left < per ? left : per);
-            s.gbase = base;
-          } else {
-            s.exhausted = 1;
-          }
+          take_input(a, s);
         }
       }
       __syncthreads();
@@ -1754,7 +1779,7 @@ __device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
       if (mode == 1) {
         ent = s.lq[(bhead + tid) & (kLq - 1)];
       } else {
-        const int2 e = load_at(a, in_list, s.gbase + (unsigned)tid);
+        const int2 e = load_at(a, list_of(a, s.team, s.in_kind, s.in_index), s.gbase + (unsigned)tid);
         ent = make_int4(e.x, e.y, 0, 0);
       }
     }
@@ -1778,6 +1803,7 @@ __device__ void decide(const Args& a) {
   Ctl* c = a.ctl;
   const int lane = (int)lane_id();
   const int K = a.K;
+  const int T = a.teams;
   const unsigned cur = ld_dev(&c->c.cur);
   const int in_kind = (int)ld_dev(&c->c.in_kind), in_index = (int)ld_dev(&c->c.in_index);
   const unsigned round = ld_dev(&c->c.round) + 1;
@@ -1785,25 +1811,42 @@ __device__ void decide(const Args& a) {
   int status = (int)ld_dev(&c->status.v);
   const int far_in = in_kind == kInFar ? 1 - in_index : (int)ld_dev(&c->c.far_in);
   const int so = (int)ld_dev(&c->c.spill_out);
-  const unsigned spill_raw = ld_dev(&c->spill_tail[so].v);
-  const unsigned far_raw = ld_dev(&c->far_tail[far_in].v);
-  const unsigned fmin = far_raw ? ld_dev(&c->far_min[far_in].v) : kNoBucket;
+  // the pending spill and far lists over all teams: total fill, largest
+  // single fill, smallest far bucket
+  unsigned spill_raw = 0, far_raw = 0, fmin = kNoBucket, need_l = 0;
+  for (int t = 0; t < T; ++t) {
+    const unsigned sr = ld_dev(&c->tq[t].spill_tail[so].v);
+    const unsigned fr = ld_dev(&c->tq[t].far_tail[far_in].v);
+    spill_raw += sr;
+    far_raw += fr;
+    need_l = sr > need_l ? sr : need_l;
+    need_l = fr > need_l ? fr : need_l;
+    if (fr) {
+      const unsigned fm = ld_dev(&c->tq[t].far_min[far_in].v);
+      fmin = fm < fmin ? fm : fmin;
+    }
+  }
   unsigned hout = 0, heavy_raw = 0;
   if constexpr (W::kSplit) {
     hout = ld_dev(&c->c.hout);
     heavy_raw = ld_dev(&c->heavy_tail[hout].v);
   }
-  // window occupancy, lane j looks at bucket cur + j
-  unsigned wraw = 0;
+  // window occupancy, lane j looks at bucket cur + j in every team
+  unsigned wraw = 0, wmax = 0;
   bool nonempty = false;
   if (lane < K) {
     const unsigned slot = (cur + (unsigned)lane) & (unsigned)(K - 1);
     const bool consumed = in_kind == kInWin && (int)slot == in_index;
-    wraw = consumed ? 0u : ld_dev(&c->win_tail[slot].v);
+    if (!consumed)
+      for (int t = 0; t < T; ++t) {
+        const unsigned x = ld_dev(&c->tq[t].win_tail[slot].v);
+        wraw += x;
+        wmax = x > wmax ? x : wmax;
+      }
     const unsigned bk = cur + (unsigned)lane;
     nonempty = wraw > 0 && bk >= cur && bk < win_hi;
   }
-  unsigned long long need_w = wraw;
+  unsigned long long need_w = wmax;
   for (int o = 32; o >= 1; o >>= 1) {
     unsigned long long y = __shfl_xor(need_w, o);
     need_w = need_w > y ? need_w : y;
@@ -1821,23 +1864,23 @@ __device__ void decide(const Args& a) {
   }
   const unsigned slot_cur_cnt = __shfl(wraw, 0);
   const unsigned long long ne = __ballot(nonempty) & ~1ull;  // buckets after cur
-  // The consumed input list's chunks go back to the pool (every lane takes a
-  // share of its chunk table).  After a failure the call ends and the pool is
-  // rebuilt by the next one.
+  // The consumed input list's chunks, in every team, go back to the pool
+  // (every lane takes a share of each chunk table).  After a failure the
+  // call ends and the pool is rebuilt by the next one.
   if (!(W::kSplit && in_kind == kInHeavy)) {
-    const unsigned* tail = in_kind == kInWin ? &c->win_tail[in_index].v
-                         : in_kind == kInSpill ? &c->spill_tail[in_index].v
-                                               : &c->far_tail[in_index].v;
-    const unsigned raw = ld_dev(tail);
-    const unsigned used = raw < a.cap ? raw : a.cap;
-    const unsigned nch = (used + kChunk - 1) >> kChunkLog;
-    const int top = (int)ld_dev(&c->free_top.v);
+    int top = (int)ld_dev(&c->free_top.v);
     if (lane == 0) {
       const unsigned taken = (unsigned)((int)a.pool_chunks - top);
       if (taken > ld_dev(&c->pool_peak.v)) st_dev(&c->pool_peak.v, taken);
     }
-    if (status == 0) {
-      unsigned* tab = chunk_slot(a, list_of(a, in_kind, in_index), 0);
+    for (int t = 0; t < T && status == 0; ++t) {
+      const unsigned* tail = in_kind == kInWin ? &c->tq[t].win_tail[in_index].v
+                           : in_kind == kInSpill ? &c->tq[t].spill_tail[in_index].v
+                                                 : &c->tq[t].far_tail[in_index].v;
+      const unsigned raw = ld_dev(tail);
+      const unsigned used = raw < a.cap ? raw : a.cap;
+      const unsigned nch = (used + kChunk - 1) >> kChunkLog;
+      unsigned* tab = chunk_slot(a, list_of(a, t, in_kind, in_index), 0);
       bool bad = top < 0 || (unsigned)top + nch > a.pool_chunks;
       for (unsigned j = (unsigned)lane; j < nch && !bad; j += kWave) {
         const int ch = (int)ld_dev(tab + j);
@@ -1851,21 +1894,25 @@ __device__ void decide(const Args& a) {
       if (__ballot(bad)) {
         status = OG_ERR_INTERNAL;  // a chunk table disagrees with its list's fill
         if (lane == 0) set_status(c, status);
-      } else if (lane == 0) {
-        st_dev(&c->free_top.v, (unsigned)(top + (int)nch));
+      } else {
+        top += (int)nch;
       }
     }
+    if (status == 0 && lane == 0) st_dev(&c->free_top.v, (unsigned)top);
   }
   if (lane != 0) return;
-  // the consumed input list is empty again
-  if (in_kind == kInWin) st_dev(&c->win_tail[in_index].v, 0);
-  else if (in_kind == kInSpill) st_dev(&c->spill_tail[in_index].v, 0);
-  else if (W::kSplit && in_kind == kInHeavy) st_dev(&c->heavy_tail[in_index].v, 0);
-  else {
-    st_dev(&c->far_tail[in_index].v, 0);
-    st_dev(&c->far_min[in_index].v, kNoBucket);
+  // the consumed input list is empty again, in every team
+  for (int t = 0; t < T; ++t) {
+    TeamQ& q = c->tq[t];
+    if (in_kind == kInWin) st_dev(&q.win_tail[in_index].v, 0);
+    else if (in_kind == kInSpill) st_dev(&q.spill_tail[in_index].v, 0);
+    else if (!(W::kSplit && in_kind == kInHeavy)) {
+      st_dev(&q.far_tail[in_index].v, 0);
+      st_dev(&q.far_min[in_index].v, kNoBucket);
+    }
+    st_dev(&q.in_head.v, 0);
   }
-  st_dev(&c->in_head.v, 0);
+  if (W::kSplit && in_kind == kInHeavy) st_dev(&c->heavy_tail[in_index].v, 0);
   st_dev(&c->buf_tail.v, 0);
   // a consumed far list hands its role to the other one (next generation)
   st_dev(&c->c.far_gen, ld_dev(&c->c.far_gen) + (in_kind == kInFar ? 1u : 0u));
@@ -1876,15 +1923,16 @@ __device__ void decide(const Args& a) {
 
   unsigned long long need = __hip_atomic_load(&c->need.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (need_w > need) need = need_w;
-  if (spill_raw > need) need = spill_raw;
-  if (far_raw > need) need = far_raw;
+  if (need_l > need) need = need_l;
   __hip_atomic_store(&c->need.v, need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
+  // (count: the one team's input size; more teams read theirs below)
   auto clampcap = [&](unsigned x) { return x < a.cap ? x : a.cap; };
   unsigned done = 0;
   unsigned ncur = cur, count = 0, buckets = ld_dev(&c->c.buckets), nwin_hi = win_hi;
   int nkind = kInWin, nindex = 0, nspill_out = so;
   unsigned nhout = hout;
+  bool heavy_next = false;
   if (status != 0) {
     done = 1;
   } else if (a.max_rounds && round >= a.max_rounds) {
@@ -1910,6 +1958,7 @@ __device__ void decide(const Args& a) {
     nkind = kInHeavy;
     nindex = (int)hout;
     nhout = 1u - hout;
+    heavy_next = true;
     count = heavy_raw < a.hcap ? heavy_raw : a.hcap;
   } else {
     const unsigned wnext = ne ? cur + (unsigned)(__ffsll((long long)ne) - 1) : kNoBucket;
@@ -1929,15 +1978,35 @@ __device__ void decide(const Args& a) {
       } else {
         nkind = kInWin;
         nindex = (int)(next & (unsigned)(K - 1));
-        count = clampcap(ld_dev(&c->win_tail[nindex].v));
+        if (T == 1) count = clampcap(ld_dev(&c->tq[0].win_tail[nindex].v));
       }
       nwin_hi = sat_add(next, (unsigned)K);
+    }
+  }
+  // each team's share of the next round's input (a heavy list is shared:
+  // the split instantiation runs one team)
+  unsigned total = count;
+  if (T == 1) {
+    st_dev(&c->tq[0].in_count.v, done ? 0u : count);
+  } else {
+    total = 0;
+    for (int t = 0; t < T; ++t) {
+      unsigned cnt = 0;
+      if (!done && !heavy_next) {
+        const TeamQ& q = c->tq[t];
+        cnt = clampcap(nkind == kInFar ? ld_dev(&q.far_tail[nindex].v)
+                     : nkind == kInSpill ? ld_dev(&q.spill_tail[nindex].v)
+                                         : ld_dev(&q.win_tail[nindex].v));
+      } else if (heavy_next) {
+        cnt = count;
+      }
+      st_dev(&c->tq[t].in_count.v, cnt);
+      total += cnt;
     }
   }
   st_dev(&c->c.cur, ncur);
   st_dev(&c->c.in_kind, (unsigned)nkind);
   st_dev(&c->c.in_index, (unsigned)nindex);
-  st_dev(&c->c.in_count, count);
   st_dev(&c->c.spill_out, (unsigned)nspill_out);
   st_dev(&c->c.far_in, (unsigned)far_in);
   st_dev(&c->c.win_hi, nwin_hi);
@@ -1946,7 +2015,7 @@ __device__ void decide(const Args& a) {
     if (nhout != hout) st_dev(&c->c.hgen, ld_dev(&c->c.hgen) + 1u);
     st_dev(&c->c.hout, nhout);
   }
-  if constexpr (W::kPull) st_dev(&c->c.pull, done ? 0u : pull_round(a, count));
+  if constexpr (W::kPull) st_dev(&c->c.pull, done ? 0u : pull_round(a, total));
   if constexpr (W::kBlocks) {
     st_dev(&c->blk_out.v, (unsigned)a.nwg);  // one input-scan token per workgroup
     st_dev(&c->blk_head.v, 0u);              // ring positions restart
@@ -1956,13 +2025,21 @@ __device__ void decide(const Args& a) {
   st_dev(&c->c.round, round);
 }
 
+// The workgroup's team (thread 0, once at the start of a kernel).
+template <class S>
+__device__ void init_team(const Args& a, S& s) {
+  s.team = (int)blockIdx.x % a.teams;
+  s.team_rank = (int)blockIdx.x / a.teams;
+  s.team_size = (a.nwg - s.team + a.teams - 1) / a.teams;
+}
+
 template <class W, class S>
 __device__ void load_control(const Args& a, S& s) {
   Ctl* c = a.ctl;
   s.cur = ld_dev(&c->c.cur);
   s.in_kind = (int)ld_dev(&c->c.in_kind);
   s.in_index = (int)ld_dev(&c->c.in_index);
-  s.in_count = ld_dev(&c->c.in_count);
+  s.in_count = ld_dev(&c->tq[s.team].in_count.v);
   s.win_hi = ld_dev(&c->c.win_hi);
   s.spill_out = (int)ld_dev(&c->c.spill_out);
   s.round = ld_dev(&c->c.round);
@@ -1986,9 +2063,14 @@ __device__ void load_control(const Args& a, S& s) {
 // wave 0) publishes the new barrier count on kFlags release flags.  With
 // wait_others (the persistent engine) every other workgroup spins on one of
 // those flags; the host-driven engine ends the kernel instead.
+__device__ void flush_counters(const Args& a, Counters& c);
+
 template <class W, class S>
 __device__ void round_barrier(const Args& a, S& s, Counters& c, bool wait_others, bool decide_next) {
   Ctl* ctl = a.ctl;
+  // a wavefront whose 32-bit counts near 2^31 adds them to the totals now
+  if (__ballot((c.relax | c.improve | c.push_local | c.push_global | c.far | c.batches) >= 0x80000000u))
+    flush_counters(a, c);
   if (threadIdx.x == 0) atomicMax(&ctl->round_max_batches.v, c.round_batches);
   c.round_batches = 0;
   wait_vm();
@@ -2026,7 +2108,9 @@ __device__ void round_barrier(const Args& a, S& s, Counters& c, bool wait_others
   if (threadIdx.x == 0) s.epoch = next;
 }
 
-__device__ void flush_counters(const Args& a, const Counters& c) {
+// Adds the wavefront's counts to the totals (all 64 lanes call it together)
+// and clears them.
+__device__ void flush_counters(const Args& a, Counters& c) {
   unsigned long long v[5] = {c.relax, c.improve, c.push_local, c.push_global, c.far};
 #pragma unroll
   for (int i = 0; i < 5; ++i)
@@ -2036,8 +2120,10 @@ __device__ void flush_counters(const Args& a, const Counters& c) {
 #pragma unroll
     for (int i = 0; i < 5; ++i)
       if (v[i]) atomicAdd(&ctl->st[kStRelax + i].v, v[i]);
-    if (threadIdx.x == 0 && c.batches) atomicAdd(&ctl->st[kStBatches].v, c.batches);
+    if (threadIdx.x == 0 && c.batches) atomicAdd(&ctl->st[kStBatches].v, (unsigned long long)c.batches);
   }
+  c.relax = c.improve = c.push_local = c.push_global = c.far = 0;
+  if (threadIdx.x == 0) c.batches = 0;
 }
 
 // ---------------------------------------------------------------- kernels
@@ -2076,9 +2162,19 @@ __global__ __launch_bounds__(kBlock) void k_init_sources(Args a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.nsrc; i += gridDim.x * blockDim.x) {
     const int s = a.srcs[i];
     a.dist[s] = 0;
-    // far list 0's first chunks are chunks 0, 1, ... of the pool (k_pool_init)
-    st_entry(a.pool, (size_t)i, s, 0);
-    atomicMin(&c->far_min[0].v, W::bucket(a, W::key(a, s, 0)));
+    if (a.teams == 1) {
+      // far list 0's first chunks are chunks 0, 1, ... of the pool (k_pool_init)
+      st_entry(a.pool, (size_t)i, s, 0);
+      atomicMin(&c->tq[0].far_min[0].v, W::bucket(a, W::key(a, s, 0)));
+    } else {
+      // the source's team files it in its far list 0 (every writer of a
+      // chunk's first position in this launch is running, so the chunk
+      // hand-over of store_at cannot wait on a thread that has not started)
+      const int t = query_of(a, s) % a.teams;
+      const unsigned pos = atomicAdd(&c->tq[t].far_tail[0].v, 1u);
+      store_at(a, list_of(a, t, kInFar, 0), pos, s, 0);
+      atomicMin(&c->tq[t].far_min[0].v, W::bucket(a, W::key(a, s, 0)));
+    }
   }
 }
 
@@ -2171,16 +2267,16 @@ __global__ __launch_bounds__(kBlock) void k_init_core(Args a) {
     const unsigned y = __shfl_xor(lo, o);
     lo = y < lo ? y : lo;
   }
-  if (lane_id() == 0 && lo != kNoBucket) atomicMin(&a.ctl->far_min[0].v, lo);
+  if (lane_id() == 0 && lo != kNoBucket) atomicMin(&a.ctl->tq[0].far_min[0].v, lo);
 }
 
 // The queue pool at the start of a call: every chunk table entry empty but
-// far list 0's first `pre` (chunks 0 .. pre-1, where the sources or, for
-// k-core, all vertices are filed), the other chunks on the free stack.  Runs
-// after the control block is zeroed.
+// team 0's far list 0's first `pre` (chunks 0 .. pre-1, where a single
+// team's sources or, for k-core, all vertices are filed), the other chunks
+// on the free stack.  Runs after the control block is zeroed.
 __global__ __launch_bounds__(kBlock) void k_pool_init(Args a, unsigned pre) {
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-  const unsigned long long ntab = (unsigned long long)(a.K + 4) * a.tchunks;
+  const unsigned long long ntab = (unsigned long long)a.teams * (a.K + 4) * a.tchunks;
   const int far0 = a.K + 2;
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntab; i += stride) {
     const unsigned j = (unsigned)(i % a.tchunks);
@@ -2198,23 +2294,28 @@ __global__ __launch_bounds__(kBlock) void k_pool_init(Args a, unsigned pre) {
 __global__ void k_init_ctl(Args a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Ctl* c = a.ctl;
-  const unsigned b0 = c->far_min[0].v;
+  unsigned b0 = kNoBucket, most = 0;
+  if (a.teams == 1) c->tq[0].far_tail[0].v = (unsigned)a.nsrc;  // (more teams: counted by k_init_sources)
+  for (int t = 0; t < a.teams; ++t) {
+    TeamQ& q = c->tq[t];
+    b0 = q.far_min[0].v < b0 ? q.far_min[0].v : b0;
+    q.in_count.v = q.far_tail[0].v;
+    most = q.far_tail[0].v > most ? q.far_tail[0].v : most;
+    q.far_min[1].v = kNoBucket;
+  }
   c->c.cur = b0;
   c->c.in_kind = kInFar;
   c->c.in_index = 0;
-  c->c.in_count = (unsigned)a.nsrc;
   c->c.far_in = 0;
   c->c.win_hi = sat_add(b0, (unsigned)a.K);
   c->c.buckets = 1;
-  c->far_tail[0].v = (unsigned)a.nsrc;
-  c->far_min[1].v = kNoBucket;
-  c->need.v = (unsigned)a.nsrc;
+  c->need.v = most;
   c->blk_out.v = (unsigned)a.nwg;  // vertex blocks: one input-scan token per workgroup
 }
 
 // Pull instantiations: the direction of the first round.
 __global__ void k_init_pull(Args a) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctl->c.pull = pull_round(a, a.ctl->c.in_count);
+  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctl->c.pull = pull_round(a, a.ctl->tq[0].in_count.v);
 }
 
 // Pull instantiations: the slices of every row longer than kLongRow, as
@@ -2238,7 +2339,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_slices(Args a, int2* slices) {
 }
 
 __global__ void k_far_min_init(Ctl* c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) c->far_min[0].v = kNoBucket;
+  if (threadIdx.x < kMaxTeams && blockIdx.x == 0) c->tq[threadIdx.x].far_min[0].v = kNoBucket;
 }
 
 // OG_FLAG_VALIDATE: the CSR structure (row_ptr[0] = 0, non-decreasing,
@@ -2294,13 +2395,16 @@ __global__ void k_validate_sym_verdict(Ctl* ctl) {
 // device-wide barrier whose last arriver takes the bucket decision.  A lazy
 // round has a second barrier between recording the changes and filing them.
 template <class W>
-__global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
+__global__ __launch_bounds__(kBlock, W::kMinWaves) void k_persistent(Args a) {
   __shared__ Smem s;
   Counters c;
   if constexpr (W::kBin) {
     if (threadIdx.x == 0) s.flat_any = 0;
   }
-  if (threadIdx.x == 0) load_control<W>(a, s);
+  if (threadIdx.x == 0) {
+    init_team(a, s);
+    load_control<W>(a, s);
+  }
   __syncthreads();
   while (!s.done) {
     if (W::kPull && s.pull) {
@@ -2335,7 +2439,10 @@ __global__ __launch_bounds__(kBlock) void k_round(Args a, int phase) {
   if constexpr (W::kBin) {
     if (threadIdx.x == 0) s.flat_any = 0;
   }
-  if (threadIdx.x == 0) load_control<W>(a, s);
+  if (threadIdx.x == 0) {
+    init_team(a, s);
+    load_control<W>(a, s);
+  }
   __syncthreads();
   if (s.done) return;
   if constexpr (W::kPull) {
@@ -2420,6 +2527,7 @@ struct BlkSmem {
   // wave_push_global use)
   unsigned cur, in_count, win_hi, round, epoch, far_stamp;
   int in_kind, in_index, done, spill_out, far_out;
+  int team, team_rank, team_size;  // this workgroup's team, its index in it, the team's workgroups
   int hout;
   unsigned hgen;
   int pull;
@@ -2801,10 +2909,11 @@ __device__ void blk_process(const Args& a, BlkSmem& s, Counters& c, int b) {
 template <class W>
 __device__ void run_round_blocks(const Args& a, BlkSmem& s, Counters& c) {
   const int tid = threadIdx.x;
-  const int in_list = list_of(a, s.in_kind, s.in_index);
+  const int in_list = list_of(a, s.team, s.in_kind, s.in_index);
   const unsigned count = s.in_count;
-  const bool fixed = count <= (unsigned)a.nwg * (unsigned)kBlock;
-  const unsigned per = fixed ? (count + (unsigned)a.nwg - 1) / (unsigned)a.nwg : (unsigned)kBlock;
+  const unsigned tsize = (unsigned)s.team_size;
+  const bool fixed = count <= tsize * (unsigned)kBlock;
+  const unsigned per = fixed ? (count + tsize - 1) / tsize : (unsigned)kBlock;
   const unsigned cur = s.cur;
   if (tid == 0) s.exhausted = 0;
   for (;;) {
@@ -2814,10 +2923,10 @@ __device__ void run_round_blocks(const Args& a, BlkSmem& s, Counters& c) {
       if (!s.exhausted) {
         unsigned base;
         if (fixed) {
-          base = (unsigned)blockIdx.x * per;
+          base = (unsigned)s.team_rank * per;
           s.exhausted = 1;
         } else {
-          base = atomicAdd(&a.ctl->in_head.v, (unsigned)kBlock);
+          base = atomicAdd(&a.ctl->tq[s.team].in_head.v, (unsigned)kBlock);
         }
         if (base < count) {
           s.mode = 2;
@@ -2875,7 +2984,10 @@ template <class W>
 __global__ __launch_bounds__(kBlock) void k_blocks(Args a) {
   __shared__ BlkSmem s;
   Counters c;
-  if (threadIdx.x == 0) load_control<W>(a, s);
+  if (threadIdx.x == 0) {
+    init_team(a, s);
+    load_control<W>(a, s);
+  }
   __syncthreads();
   while (!s.done) {
     run_round_blocks<W>(a, s, c);
@@ -3611,10 +3723,26 @@ size_t table_bytes(const Shape& sh) {
   return (b + 255) & ~(size_t)255;
 }
 
+// Teams a call may split its workgroups into (its workspace holds their
+// lists): a batched launch of the eager push engine, schedule.teams (0 =
+// 2 from 8 queries on, 4 from 32: the fastest on the road grid, where 8
+// teams of one XCD each leave too few workgroups per query), at most one
+// per query; any other call one.  The launch runs min(that, workgroups).
+int team_cap(const og_schedule* r, const Shape& sh) {
+  if (sh.core || sh.reps < 2 || r->update == OG_LAZY_UPDATE) return 1;
+  if (r->flags & (OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION | OG_FLAG_VERTEX_BLOCKS))
+    return 1;
+  int t = r->teams > 0 ? r->teams : (sh.reps >= 32 ? 4 : sh.reps >= 8 ? 2 : 1);
+  if (t > kMaxTeams) t = kMaxTeams;
+  if (t > sh.reps) t = sh.reps;
+  return t;
+}
+
 // The global lists' pool, from byte offset off: the chunk tables (one per
-// list, tchunks entries each), the free stack and the chunks.  Far list 0
-// starts with chunks 0 .. pre-1, which hold the sources (k-core: every
-// vertex).  Pool size: schedule.queue_pool entries rounded up to whole
+// list of each team, tchunks entries each), the free stack and the chunks.
+// When the call runs one team, far list 0 starts with chunks 0 .. pre-1,
+// which hold the sources (k-core: every vertex); with more, each source
+// takes its chunk through the usual hand-over.  Pool size: schedule.queue_pool entries rounded up to whole
 // chunks, by default twice one list's capacity plus one chunk per list (the
 // partly filled last chunks), never more than every list full at once, and
 // never fewer than the sources' chunks plus one.
@@ -3623,12 +3751,12 @@ struct PoolLayout {
   size_t ctab, fstack, pool, end;
 };
 
-PoolLayout pool_layout(const og_schedule* r, const Shape& sh, long long cap, size_t off) {
+PoolLayout pool_layout(const og_schedule* r, const Shape& sh, long long cap, int teams, size_t off) {
   PoolLayout L;
   const long long ck = (long long)kChunk;
-  const long long lists = (long long)r->window_buckets + 4;  // K window slots, 2 spill, 2 far
+  const long long lists = (long long)teams * (r->window_buckets + 4);  // per team: K window slots, 2 spill, 2 far
   L.tchunks = (unsigned)((cap + ck - 1) / ck);
-  L.pre = (unsigned)(((long long)sh.nsrc + ck - 1) / ck);
+  L.pre = (unsigned)(((long long)sh.nsrc + ck - 1) / ck);  // far list 0's first chunks when one team runs
   long long ch = r->queue_pool > 0 ? (r->queue_pool + ck - 1) / ck : (2 * cap + ck - 1) / ck + lists;
   if (ch > lists * (long long)L.tchunks) ch = lists * (long long)L.tchunks;
   if (ch < (long long)L.pre + 1) ch = (long long)L.pre + 1;
@@ -3710,7 +3838,7 @@ size_t vec_bytes(long long n) { return ((size_t)n * sizeof(int) + 255) & ~(size_
 
 size_t ws_bytes_for(const og_graph* g, const og_schedule* r, const Shape& sh) {
   const long long cap = queue_cap(g, r, sh);
-  size_t b = pool_layout(r, sh, cap, kCtlBytes + table_bytes(sh)).end;
+  size_t b = pool_layout(r, sh, cap, team_cap(r, sh), kCtlBytes + table_bytes(sh)).end;
   const long long nv = (long long)sh.reps * g->n;
   if (r->update == OG_LAZY_UPDATE) b += 2 * vec_bytes(nv);
   if (sh.core) b += vec_bytes(nv);
@@ -3735,7 +3863,8 @@ bool schedule_ok(const og_schedule* s) {
   if (s->window_buckets == 1) return false;
   if (s->engine != OG_ENGINE_PERSISTENT && s->engine != OG_ENGINE_HOST_ROUNDS && s->engine != OG_ENGINE_GRAPH_ROUNDS)
     return false;
-  if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0 || s->queue_pool < 0) return false;
+  if (s->max_rounds < 0 || s->workgroups < 0 || s->queue_capacity < 0 || s->queue_pool < 0 || s->teams < 0)
+    return false;
   if (s->flags & ~(OG_FLAG_VALIDATE | OG_FLAG_ASYNC | OG_FLAG_TIMING | OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL |
                    OG_FLAG_HYBRID_DIRECTION | OG_FLAG_DEGREE_BINS | OG_FLAG_KEEP_SPLIT | OG_FLAG_VERTEX_BLOCKS |
                    OG_FLAG_KEEP_BLOCKS))
@@ -4041,7 +4170,9 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   a.max_rounds = (unsigned)r.max_rounds;
   a.nwg = nwg;
   a.ctl = (Ctl*)base;
-  const PoolLayout pl = pool_layout(&r, sh, cap, kCtlBytes + table_bytes(sh));
+  const int tmax = team_cap(&r, sh);
+  const PoolLayout pl = pool_layout(&r, sh, cap, tmax, kCtlBytes + table_bytes(sh));
+  a.teams = tmax < nwg ? tmax : nwg;
   a.ctab = (int*)(base + pl.ctab);
   a.fstack = (int*)(base + pl.fstack);
   a.pool = (int2*)(base + pl.pool);
@@ -4148,17 +4279,19 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
   }
   const int fill_grid = di.cus * 8;
   const int src_grid = (sh.nsrc + kBlock - 1) / kBlock;
+  const unsigned pre = a.teams == 1 ? pl.pre : 0u;  // more teams: sources take chunks as they are filed
   const int pool_grid = (int)std::min<long long>(
-      fill_grid, ((long long)std::max<size_t>((size_t)(a.K + 4) * pl.tchunks, pl.chunks) + kBlock - 1) / kBlock);
+      fill_grid,
+      ((long long)std::max<size_t>((size_t)a.teams * (a.K + 4) * pl.tchunks, pl.chunks) + kBlock - 1) / kBlock);
   if constexpr (W::kCore) {
     hipLaunchKernelGGL(k_zero_ctl, dim3(16), dim3(kBlock), 0, stream, a.ctl);
     hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
-    hipLaunchKernelGGL(k_pool_init, dim3(pool_grid), dim3(kBlock), 0, stream, a, pl.pre);
+    hipLaunchKernelGGL(k_pool_init, dim3(pool_grid), dim3(kBlock), 0, stream, a, pre);
     hipLaunchKernelGGL(k_init_core, dim3(fill_grid), dim3(kBlock), 0, stream, a);
   } else {
     hipLaunchKernelGGL(k_init, dim3(fill_grid), dim3(kBlock), 0, stream, a, (int)W::kInfBits);
     hipLaunchKernelGGL(k_far_min_init, dim3(1), dim3(kWave), 0, stream, a.ctl);
-    hipLaunchKernelGGL(k_pool_init, dim3(pool_grid), dim3(kBlock), 0, stream, a, pl.pre);
+    hipLaunchKernelGGL(k_pool_init, dim3(pool_grid), dim3(kBlock), 0, stream, a, pre);
     hipLaunchKernelGGL(k_init_sources<PW>, dim3(src_grid), dim3(kBlock), 0, stream, a);
   }
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, stream, a);

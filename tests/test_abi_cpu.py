@@ -65,13 +65,16 @@ def _fake_graph(n=10, m=20):
     return _lib.OgGraph(n, m, 0x1000, 0x2000, 0x3000)
 
 
-def _queues(cap, k, nsrc=1, pool=0):
-    """Bytes of the global queues: per-queue chunk tables, the free stack and
-    the pool of 4,096-entry chunks (default: twice one queue's capacity plus
-    one chunk per queue, at most every queue full, at least the sources'
-    chunks plus one), each region 256-byte aligned."""
+CTL = 131072  # the control block: counters, flags and each team's queue tails
+
+
+def _queues(cap, k, nsrc=1, pool=0, teams=1):
+    """Bytes of the global queues: per-queue chunk tables (K + 4 queues per
+    team), the free stack and the pool of 4,096-entry chunks (default: twice
+    one queue's capacity plus one chunk per queue, at most every queue full,
+    at least the sources' chunks plus one), each region 256-byte aligned."""
     ck = 4096
-    lists = k + 4
+    lists = teams * (k + 4)
     tch = -(-cap // ck)
     pre = -(-nsrc // ck)
     ch = -(-pool // ck) if pool > 0 else -(-2 * cap // ck) + lists
@@ -88,23 +91,23 @@ def test_workspace_bytes():
     g = _fake_graph(1000, 4000)
     s = og.Schedule(delta=4).to_c()
     b = lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s))
-    assert b % 256 == 0 and b >= 65536 + (16 + 4) * 1024 * 8
+    assert b % 256 == 0 and b >= CTL + (16 + 4) * 1024 * 8
     s2 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000).to_c()
     Q = _queues(5000, 8)
-    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == 65536 + 256 + Q
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s2)) == CTL + 256 + Q
     # an explicit pool size, rounded up to whole chunks and clamped to the queues' total
     for pool, want in ((1, 2), (9000, 3), (10 ** 9, 24)):
         sp = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, queue_pool=pool).to_c()
-        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(sp)) == 65536 + 256 + _queues(5000, 8, pool=pool)
+        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(sp)) == CTL + 256 + _queues(5000, 8, pool=pool)
         assert _queues(5000, 8, pool=pool) == 256 + (4 * want + 255) // 256 * 256 + 8 * 4096 * want
     neg = og.Schedule(delta=4, queue_pool=-1).to_c()
     assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(neg)) == 0
     # lazy update: + change flags and change buffer, one int per vertex each
     s3 = og.Schedule(delta=4, window_buckets=8, queue_capacity=5000, update=og.OG_LAZY_UPDATE).to_c()
     vec = (g.n * 4 + 255) // 256 * 256
-    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s3)) == 65536 + 256 + Q + 2 * vec
+    assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s3)) == CTL + 256 + Q + 2 * vec
     # k-core: no source table; + peel marks (and the lazy arrays)
-    base = 65536 + Q
+    base = CTL + Q
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s2)) == base + vec
     assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s3)) == base + 3 * vec
     # light/heavy split: + split copy of col and w, light counts, long-row
@@ -114,7 +117,7 @@ def test_workspace_bytes():
     for gs in (g, _fake_graph(1000, 100_000)):
         evec = (gs.m * 4 + 255) // 256 * 256
         hvec = ((gs.n + gs.m // 4096 + 1) * 4 + 255) // 256 * 256
-        assert lib.og_workspace_bytes(ctypes.byref(gs), ctypes.byref(s4)) == (65536 + 256 + Q
+        assert lib.og_workspace_bytes(ctypes.byref(gs), ctypes.byref(s4)) == (CTL + 256 + Q
                                                                               + 2 * evec + 3 * vec + 4 * hvec)
     # pull direction (lazy only): + frontier marks (SSSP: 8 bytes per vertex; k-core: one bit) and the
     # long rows' slice list
@@ -123,7 +126,7 @@ def test_workspace_bytes():
         marks = (g.n * 8 + 255) // 256 * 256
         bits = ((g.n + 31) // 32 * 4 + 255) // 256 * 256
         slices = ((g.m // 2048 + g.m // 8192 + 1) * 8 + 255) // 256 * 256
-        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s5)) == (65536 + 256 + Q + 2 * vec
+        assert lib.og_workspace_bytes(ctypes.byref(g), ctypes.byref(s5)) == (CTL + 256 + Q + 2 * vec
                                                                              + marks + slices)
         assert lib.og_workspace_bytes_kcore(ctypes.byref(g), ctypes.byref(s5)) == base + 3 * vec + bits + slices
     lazy_split = og.Schedule(delta=4, update=og.OG_LAZY_UPDATE, flags=og.OG_FLAG_LIGHT_HEAVY).to_c()
@@ -135,6 +138,28 @@ def test_workspace_bytes():
     assert lib.og_workspace_bytes(ctypes.byref(g0), ctypes.byref(s)) == 0
 
 
+def test_batch_workspace_holds_every_teams_queues():
+    """A batched call of the eager push engine sizes its queues for its teams
+    (schedule.teams; by default 2 from 8 queries, 4 from 32; at most 8 and
+    one per query); the lazy update and the split, pull and block variants
+    keep one team."""
+    lib = _lib.load()
+    g = _fake_graph(1000, 4000)
+    table = lambda nq: (4 * (nq + nq) + 255) // 256 * 256  # sources and targets
+    per = 1000 + 4000 // 8
+    for nq, teams, want in ((8, 0, 2), (3, 0, 1), (16, 0, 2), (32, 0, 4), (64, 0, 4), (8, 1, 1), (8, 4, 4),
+                            (8, 99, 8), (3, 8, 3)):
+        s = og.Schedule(delta=4, window_buckets=8, teams=teams).to_c()
+        got = lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(s), nq)
+        assert got == CTL + table(nq) + _queues(nq * per + nq, 8, nsrc=nq, teams=want), (nq, teams)
+    lazy = og.Schedule(delta=4, window_buckets=8, update=og.OG_LAZY_UPDATE).to_c()
+    vec = (8 * 1000 * 4 + 255) // 256 * 256
+    assert lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(lazy), 8) == (
+        CTL + table(8) + _queues(8 * per + 8, 8, nsrc=8, teams=1) + 2 * vec)
+    neg = og.Schedule(delta=4, teams=-1).to_c()
+    assert lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(neg), 8) == 0
+
+
 @pytest.mark.parametrize("field,value", [
     ("delta", 0), ("update", 3), ("window_buckets", 1), ("window_buckets", 65), ("engine", 7),
     ("max_rounds", -1), ("flags", 1024), ("fusion_threshold", -2),
@@ -144,6 +169,8 @@ def test_workspace_bytes():
     ("bin_thread", -1), ("bin_wave", -1), ("flags", 64 | 8), ("flags", 64 | 16),
     # vertex blocks: not with the split, the degree bins or a pull direction; a non-negative block size
     ("flags", 256 | 8), ("flags", 256 | 64), ("flags", 256 | 16), ("block_size", -1),
+    # queue pool and teams: non-negative
+    ("queue_pool", -1), ("teams", -1),
 ])
 def test_invalid_schedule_rejected(field, value):
     lib = _lib.load()

@@ -47,9 +47,10 @@ def test_committed_profile_is_current():
 def test_kernel_profiles_are_current():
     """The committed kernel traces and counter summaries that stand for the
     current engine were taken on it (a code change without retaking them
-    fails here); the two older counter sets say which code they were taken on."""
+    fails here); the older stall counters say which code they were taken on."""
     current = ["k_persistent_road4096_traffic.txt", "kernels_road4096_d512_fused.txt",
                "k_persistent_road4096_batch8_traffic.txt", "kernels_road4096_batch8_d1024.txt",
+               "k_persistent_road4096_batch8_counters.txt",
                "kernels_road4096_blocks_d2048.txt", "k_persistent_road4096_bins_counters.txt",
                "kernels_kcore_rmat24_lazy.txt", "kernels_sssp_rmat24_d32_unfused.txt",
                "kernels_sssp_rmat24_split_d64_kept_counters.txt"]
