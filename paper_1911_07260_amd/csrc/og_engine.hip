@@ -371,10 +371,6 @@ struct IntW {
   static constexpr bool kPull = false;
   static constexpr bool kBin = false;
   static constexpr bool kBlocks = false;
-  // wavefronts per SIMD the persistent kernel is compiled for: 6 fits its
-  // 25.7 KB of LDS per workgroup and keeps a latency-bound road chain fed
-  // (1 = as many as its registers allow)
-  static constexpr int kMinWaves = 6;
   // nd = d + w; false (and a status) for a negative weight or a sum that
   // reaches INT32_MAX
   __device__ static bool add(const Args& a, int d, int wraw, int* nd) {
@@ -405,7 +401,6 @@ struct IntW {
 struct FloatW {
   static constexpr int kInfBits = 0x7f800000;  // +inf
   static constexpr bool kSplit = false;
-  static constexpr int kMinWaves = 1;
   static constexpr bool kWide = true;
   static constexpr bool kCore = false;
   static constexpr bool kPull = false;
@@ -456,7 +451,6 @@ struct CoreW : IntW {
 struct SplitW : IntW {
   static constexpr bool kSplit = true;
   static constexpr bool kWide = true;
-  static constexpr int kMinWaves = 1;
   __device__ static bool light(const Args& a, int wraw) { return wraw < (int)a.delta; }
 };
 
@@ -469,11 +463,9 @@ struct SplitW : IntW {
 // engines.
 struct PullW : IntW {
   static constexpr bool kPull = true;
-  static constexpr int kMinWaves = 5;
 };
 struct CorePullW : CoreW {
   static constexpr bool kPull = true;
-  static constexpr int kMinWaves = 5;
 };
 
 // Degree-binned load balancing: within a batch, a vertex of at most
@@ -1798,37 +1790,38 @@ __device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
 //   4. otherwise the next non-empty bucket (section 3.2: smallest bucket
 //      across workers), or stop (nothing left, or PPSP / A*: that bucket's
 //      lower bound i*Delta already reaches every target's distance).
-template <class W>
-__device__ void decide(const Args& a) {
+// The round's control values come from the deciding workgroup's snapshot
+// (taken at the round's start; only the decision changes them), so the
+// loads below do not wait on one another.
+template <class W, class S>
+__device__ void decide(const Args& a, const S& snap) {
   Ctl* c = a.ctl;
   const int lane = (int)lane_id();
   const int K = a.K;
   const int T = a.teams;
-  const unsigned cur = ld_dev(&c->c.cur);
-  const int in_kind = (int)ld_dev(&c->c.in_kind), in_index = (int)ld_dev(&c->c.in_index);
-  const unsigned round = ld_dev(&c->c.round) + 1;
-  const unsigned win_hi = ld_dev(&c->c.win_hi);
+  const unsigned cur = snap.cur;
+  const int in_kind = snap.in_kind, in_index = snap.in_index;
+  const unsigned round = snap.round + 1;
+  const unsigned win_hi = snap.win_hi;
   int status = (int)ld_dev(&c->status.v);
-  const int far_in = in_kind == kInFar ? 1 - in_index : (int)ld_dev(&c->c.far_in);
-  const int so = (int)ld_dev(&c->c.spill_out);
+  const int far_in = in_kind == kInFar ? 1 - in_index : snap.far_out;
+  const int so = snap.spill_out;
   // the pending spill and far lists over all teams: total fill, largest
   // single fill, smallest far bucket
   unsigned spill_raw = 0, far_raw = 0, fmin = kNoBucket, need_l = 0;
   for (int t = 0; t < T; ++t) {
     const unsigned sr = ld_dev(&c->tq[t].spill_tail[so].v);
     const unsigned fr = ld_dev(&c->tq[t].far_tail[far_in].v);
+    const unsigned fm = ld_dev(&c->tq[t].far_min[far_in].v);  // (read whether or not the list is empty)
     spill_raw += sr;
     far_raw += fr;
     need_l = sr > need_l ? sr : need_l;
     need_l = fr > need_l ? fr : need_l;
-    if (fr) {
-      const unsigned fm = ld_dev(&c->tq[t].far_min[far_in].v);
-      fmin = fm < fmin ? fm : fmin;
-    }
+    if (fr) fmin = fm < fmin ? fm : fmin;
   }
   unsigned hout = 0, heavy_raw = 0;
   if constexpr (W::kSplit) {
-    hout = ld_dev(&c->c.hout);
+    hout = (unsigned)snap.hout;
     heavy_raw = ld_dev(&c->heavy_tail[hout].v);
   }
   // window occupancy, lane j looks at bucket cur + j in every team
@@ -1874,11 +1867,9 @@ __device__ void decide(const Args& a) {
       if (taken > ld_dev(&c->pool_peak.v)) st_dev(&c->pool_peak.v, taken);
     }
     for (int t = 0; t < T && status == 0; ++t) {
-      const unsigned* tail = in_kind == kInWin ? &c->tq[t].win_tail[in_index].v
-                           : in_kind == kInSpill ? &c->tq[t].spill_tail[in_index].v
-                                                 : &c->tq[t].far_tail[in_index].v;
-      const unsigned raw = ld_dev(tail);
-      const unsigned used = raw < a.cap ? raw : a.cap;
+      // the list's fill is the team's input size of this round (it takes no
+      // entries while it is the input)
+      const unsigned used = T == 1 ? snap.in_count : ld_dev(&c->tq[t].in_count.v);
       const unsigned nch = (used + kChunk - 1) >> kChunkLog;
       unsigned* tab = chunk_slot(a, list_of(a, t, in_kind, in_index), 0);
       bool bad = top < 0 || (unsigned)top + nch > a.pool_chunks;
@@ -1914,8 +1905,9 @@ __device__ void decide(const Args& a) {
   }
   if (W::kSplit && in_kind == kInHeavy) st_dev(&c->heavy_tail[in_index].v, 0);
   st_dev(&c->buf_tail.v, 0);
-  // a consumed far list hands its role to the other one (next generation)
-  st_dev(&c->c.far_gen, ld_dev(&c->c.far_gen) + (in_kind == kInFar ? 1u : 0u));
+  // a consumed far list hands its role to the other one (next generation;
+  // the snapshot's far_stamp is the generation plus that one)
+  st_dev(&c->c.far_gen, snap.far_stamp);
   {
     const unsigned rm = __hip_atomic_exchange(&c->round_max_batches.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     atomicAdd(&c->st[kStChain].v, (unsigned long long)rm);
@@ -2012,7 +2004,7 @@ __device__ void decide(const Args& a) {
   st_dev(&c->c.win_hi, nwin_hi);
   st_dev(&c->c.buckets, buckets);
   if constexpr (W::kSplit) {
-    if (nhout != hout) st_dev(&c->c.hgen, ld_dev(&c->c.hgen) + 1u);
+    if (nhout != hout) st_dev(&c->c.hgen, snap.hgen + 1u);
     st_dev(&c->c.hout, nhout);
   }
   if constexpr (W::kPull) st_dev(&c->c.pull, done ? 0u : pull_round(a, total));
@@ -2095,7 +2087,7 @@ __device__ void round_barrier(const Args& a, S& s, Counters& c, bool wait_others
   const unsigned next = s.epoch + 1;
   if (s.last) {
     if (threadIdx.x < kWave) {
-      if (decide_next) decide<W>(a);
+      if (decide_next) decide<W>(a, s);
       if (threadIdx.x == 0) st_dev(&ctl->c.epoch, next);
       wait_vm();
       st_dev(&ctl->flag[threadIdx.x].v, next);
@@ -2395,7 +2387,7 @@ __global__ void k_validate_sym_verdict(Ctl* ctl) {
 // device-wide barrier whose last arriver takes the bucket decision.  A lazy
 // round has a second barrier between recording the changes and filing them.
 template <class W>
-__global__ __launch_bounds__(kBlock, W::kMinWaves) void k_persistent(Args a) {
+__global__ __launch_bounds__(kBlock) void k_persistent(Args a) {
   __shared__ Smem s;
   Counters c;
   if constexpr (W::kBin) {
