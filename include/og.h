@@ -187,8 +187,10 @@ typedef int32_t og_status;
 
 /* Engines. */
 #define OG_ENGINE_PERSISTENT 0 /* one cooperative launch, device-wide barrier
-                                  between rounds (default)                   */
-#define OG_ENGINE_HOST_ROUNDS 1 /* one kernel launch per round               */
+                                  between rounds (default; with teams, each
+                                  team's barrier between its own rounds)     */
+#define OG_ENGINE_HOST_ROUNDS 1 /* one kernel launch per round (with teams:
+                                  one round of every team not yet done)      */
 #define OG_ENGINE_GRAPH_ROUNDS 2 /* as _HOST_ROUNDS, the launches replayed from
                                    one executable hipGraph of 32 rounds, kept
                                    per host thread while the call's kernel,
@@ -233,27 +235,32 @@ typedef struct og_schedule {
   int64_t queue_pool;       /* entries shared by all global queues, drawn in
                                chunks of 4096 as the queues grow and returned
                                when a queue has been consumed (0 = twice
-                               queue_capacity plus one chunk per queue); an
-                               empty pool ends the call with OG_ERR_WORKSPACE */
+                               queue_capacity plus one chunk per queue); with
+                               teams, each team draws from an equal share.
+                               An empty pool (or share) ends the call with
+                               OG_ERR_WORKSPACE                               */
   int32_t teams;            /* batched calls of the eager push engine: teams
                                of workgroups (workgroup b in team b mod
-                               teams), each with its own queues and the
-                               queries q with q mod teams = team; the
-                               hardware deals consecutive workgroups to the 8
-                               XCDs in turn, so a team's work stays in the
-                               L2s of its XCDs.  0 = 1 below 8 queries, 2
-                               from 8, 4 from 32; at most 8, one per query
-                               and one per workgroup.  Other calls,
-                               OG_LAZY_UPDATE and the split, pull and block
-                               variants run one team                          */
+                               teams), each with the queries q with q mod
+                               teams = team, its own queues, pool share and
+                               rounds: a team synchronises only its own
+                               workgroups and takes its own bucket
+                               decisions.  The hardware deals consecutive
+                               workgroups to the 8 XCDs in turn, so with 8
+                               teams each XCD serves its own queries.  0 =
+                               8; at most 8, one per query and one per
+                               workgroup.  Other calls, OG_LAZY_UPDATE and
+                               the split, pull and block variants run one
+                               team                                           */
 } og_schedule;
 
 /* Per-call counters (host struct). */
 typedef struct og_stats {
   og_status status;
   int32_t workgroups;       /* workgroups launched                            */
-  int64_t rounds;           /* rounds (bucket decisions)                      */
-  int64_t buckets;          /* distinct buckets processed                     */
+  int64_t rounds;           /* rounds (bucket decisions); with teams, the
+                               most rounds one team took                      */
+  int64_t buckets;          /* distinct buckets processed, summed over teams  */
   int64_t relaxations;      /* edges examined                                 */
   int64_t improvements;     /* successful atomic minimum updates              */
   int64_t pushes_local;     /* entries appended to an LDS (fused) queue       */
@@ -269,16 +276,21 @@ typedef struct og_stats {
                                over workgroups                                */
   int64_t chain;            /* sum over rounds of the most batches any one
                                workgroup processed in that round (the engine's
-                               critical path in batch steps)                  */
+                               critical path in batch steps); with teams, the
+                               largest team's sum                             */
   int64_t barriers;         /* device-wide synchronisations: one per round, two
-                               with OG_LAZY_UPDATE                            */
+                               with OG_LAZY_UPDATE; with teams, the most one
+                               team took (each synchronises its own)          */
   int64_t blocks;           /* OG_FLAG_VERTEX_BLOCKS: blocks of the copy (the
                                activations of blocks are counted in batches)  */
   double prep_ms;           /* OG_FLAG_VERTEX_BLOCKS with OG_FLAG_TIMING: time
                                to build the blocked copy (0 when kept)        */
   int64_t pool_needed;      /* most queue-pool entries in use at once (whole
-                               chunks; after OG_ERR_WORKSPACE: the demand up
-                               to the failure)                               */
+                               chunks; with teams: the most one team held
+                               times the team count, the pool whose equal
+                               shares hold every team's peak; after
+                               OG_ERR_WORKSPACE: the demand up to the
+                               failure)                                       */
 } og_stats;
 
 /* Library version, (major << 16) | minor. */

@@ -59,6 +59,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -92,9 +93,9 @@ constexpr size_t kCtlBytes = 131072;
 // rings and pushes never mix teams.
 constexpr int kMaxTeams = 8;
 // The global bucket lists (K window slots, 2 spill lists, 2 far lists) draw
-// fixed-size chunks from one shared pool: list L's position p lives in the
-// chunk its table names for p / kChunk.  A list's chunks go back to the
-// pool when the list is consumed.
+// fixed-size chunks from a pool, each team from an equal share of its own:
+// list L's position p lives in the chunk its table names for p / kChunk.  A
+// list's chunks go back to its team's share when the list is consumed.
 constexpr int kChunkLog = 12;
 constexpr unsigned kChunk = 1u << kChunkLog;  // entries per chunk (32 KB)
 constexpr int kNoChunk = -1;    // table entry: chunk not taken yet
@@ -152,7 +153,7 @@ constexpr int kDegMask = kHeavyBit - 1;
 constexpr int kBinLane = 4;
 constexpr int kDefaultBinWave = 64;
 enum : int {
-  kStRelax, kStImprove, kStPushLocal, kStPushGlobal, kStFar, kStBatches, kStReachedV, kStReachedE, kStChain, kStCount
+  kStRelax, kStImprove, kStPushLocal, kStPushGlobal, kStFar, kStBatches, kStReachedV, kStReachedE, kStCount
 };
 
 // Every counter that many workgroups update sits on its own 128-byte line.
@@ -163,7 +164,7 @@ struct alignas(128) Word64 {
   unsigned long long v;
 };
 
-// State chosen by the bucket decision for the next round.
+// State chosen by the bucket decision for a team's next round.
 struct alignas(128) Control {
   unsigned cur;       // current bucket
   unsigned in_kind;   // round input: window slot / spill list / far list
@@ -174,7 +175,7 @@ struct alignas(128) Control {
   unsigned win_hi;     // buckets >= win_hi go to the far list
   unsigned round;
   unsigned buckets;
-  unsigned epoch;    // device-wide barriers completed
+  unsigned epoch;    // the team's barriers completed
   unsigned far_gen;  // generation of the pending far list (k-core filing)
   unsigned hout;     // light/heavy split: heavy list receiving settled vertices
   unsigned hgen;     // light/heavy split: generation of that list (heavy rounds so far)
@@ -192,25 +193,31 @@ struct TeamQ {
   Word far_min[2];
 };
 
-// Device-side control block at the start of the workspace.
+// Device-side control block at the start of the workspace.  Every team
+// runs rounds of its own: its control state, barrier counters, release
+// flags, bucket lists and share of the queue pool are its own (a launch of
+// one team uses entry 0 of each).
 struct Ctl {
-  Control c;
+  Control tc[kMaxTeams];
   Word status;
-  Word bar_root;
-  Word bar_grp[kMaxGroups];
-  Word flag[kFlags];  // release flags: the round number now allowed to start
+  Word live;  // teams not done yet (status and live are adjacent: the host-driven engine polls both)
+  Word teams;
+  Word bar_root[kMaxTeams];
+  Word bar_grp[kMaxGroups + 2 * kMaxTeams];  // each team's first-level counters, kGroup workgroups each
+  Word flag[kFlags];  // release flags, kFlags / teams per team: the round number now allowed to start
   TeamQ tq[kMaxTeams];
-  Word round_max_batches;  // most batches one workgroup ran in the current round
-  Word buf_tail;           // lazy update: entries in the change buffer
+  Word round_max_batches[kMaxTeams];  // most batches one of the team's workgroups ran in its current round
+  Word buf_tail;                      // lazy update: entries in the change buffer
   Word64 need;
   Word64 st[kStCount];
+  Word64 chain[kMaxTeams];  // per team: sum over its rounds of round_max_batches
   Word heavy_tail[2];  // light/heavy split: settled vertices per heavy list
   Word big_rows;       // light/heavy split: rows left to the wavefront split pass
   Word64 sym;          // symmetry checksum of OG_FLAG_VALIDATE with a pull direction
   Word slices;         // pull direction: row slices listed per copy of the graph
   Word64 pred_slices;  // predecessor pass: slices of long rows listed
-  Word free_top;       // free chunks on the pool's stack
-  Word pool_peak;      // most chunks taken at once (sampled at each bucket decision)
+  Word free_top[kMaxTeams];   // free chunks on each team's stack
+  Word pool_peak[kMaxTeams];  // most of the team's chunks taken at once (sampled at each bucket decision)
   Word blk_out;        // vertex blocks: work items of the round not yet finished
   Word blk_head;       // vertex blocks: ring positions taken
   Word blk_tail;       // vertex blocks: ring positions filled
@@ -241,7 +248,7 @@ struct Args {
   Ctl* ctl;
   int2* pool;         // [pool_chunks * kChunk] entries of every global list
   int* ctab;          // [teams * (K + 4) * tchunks] chunk of each list position / kChunk
-  int* fstack;        // [pool_chunks] free chunks (the bottom free_top entries)
+  int* fstack;        // [pool_chunks] free chunks: team t's stack at team_lo(t) (its bottom free_top[t] entries)
   unsigned pool_chunks;
   unsigned tchunks;   // table entries per list: ceil(cap / kChunk)
   int lazy;       // lazy bucket update: record changes, file them after a barrier
@@ -507,17 +514,26 @@ __device__ __forceinline__ int2 load_at(const Args& a, int list, unsigned pos) {
   return ld_entry(a.pool, (size_t)ch * kChunk + (pos & (kChunk - 1)));
 }
 
+// Team t's share of the pool: chunks team_lo(t) .. team_lo(t + 1) - 1, and
+// the same positions of the free stack.
+__device__ __host__ __forceinline__ unsigned team_lo(unsigned chunks, int teams, int t) {
+  return (unsigned)(((unsigned long long)t * chunks) / (unsigned)teams);
+}
+
 // Stores (v, d) at position pos (< cap) of a list.  The writer of a chunk's
-// first position takes a chunk from the pool for it; writers of the chunk's
-// other positions wait until the table names it (that writer reserved its
-// position earlier and does not wait on anything).  False when the pool was
-// empty (OG_ERR_WORKSPACE is set).
+// first position takes a chunk from its team's stack for it; writers of the
+// chunk's other positions wait until the table names it (that writer
+// reserved its position earlier and does not wait on anything).  False when
+// the team's share was empty (OG_ERR_WORKSPACE is set).
 __device__ bool store_at(const Args& a, int list, unsigned pos, int v, int d) {
   unsigned* slot = chunk_slot(a, list, pos);
   if ((pos & (kChunk - 1)) == 0) {
-    const int top = atomicSub(reinterpret_cast<int*>(&a.ctl->free_top.v), 1) - 1;
+    const int t = list / (a.K + 4);
+    const unsigned lo = team_lo(a.pool_chunks, a.teams, t);
+    const int size = (int)(team_lo(a.pool_chunks, a.teams, t + 1) - lo);
+    const int top = atomicSub(reinterpret_cast<int*>(&a.ctl->free_top[t].v), 1) - 1;
     int ch = kLostChunk;
-    if (top >= 0 && top < (int)a.pool_chunks) ch = (int)ld_dev(reinterpret_cast<const unsigned*>(a.fstack) + top);
+    if (top >= 0 && top < size) ch = (int)ld_dev(reinterpret_cast<const unsigned*>(a.fstack) + lo + top);
     else set_status(a.ctl, OG_ERR_WORKSPACE);
     st_dev(slot, (unsigned)ch);
   }
@@ -1781,15 +1797,17 @@ __device__ void run_round_binned(const Args& a, Smem& s, Counters& c) {
   }
 }
 
-// Bucket decision, executed by wave 0 of the last workgroup to finish a
-// round, while every other workgroup waits (persistent engine) or has
-// exited (host-driven engine).  Chooses the next round's input:
+// Bucket decision of one team, executed by wave 0 of the team's last
+// workgroup to finish a round, while the team's other workgroups wait
+// (persistent engine) or have exited (host-driven engine); other teams run
+// their own rounds meanwhile.  Chooses the team's next round input:
 //   1. far entries of the current bucket (overflow, or the initial sources),
 //   2. the window slot of the current bucket (after such a far round),
 //   3. the spill list: the same bucket needs another round,
 //   4. otherwise the next non-empty bucket (section 3.2: smallest bucket
 //      across workers), or stop (nothing left, or PPSP / A*: that bucket's
-//      lower bound i*Delta already reaches every target's distance).
+//      lower bound i*Delta already reaches every target of the team's
+//      queries).
 // The round's control values come from the deciding workgroup's snapshot
 // (taken at the round's start; only the decision changes them), so the
 // loads below do not wait on one another.
@@ -1799,6 +1817,9 @@ __device__ void decide(const Args& a, const S& snap) {
   const int lane = (int)lane_id();
   const int K = a.K;
   const int T = a.teams;
+  const int t0 = snap.team;
+  TeamQ& tq = c->tq[t0];
+  Control& tc = c->tc[t0];
   const unsigned cur = snap.cur;
   const int in_kind = snap.in_kind, in_index = snap.in_index;
   const unsigned round = snap.round + 1;
@@ -1806,48 +1827,37 @@ __device__ void decide(const Args& a, const S& snap) {
   int status = (int)ld_dev(&c->status.v);
   const int far_in = in_kind == kInFar ? 1 - in_index : snap.far_out;
   const int so = snap.spill_out;
-  // the pending spill and far lists over all teams: total fill, largest
-  // single fill, smallest far bucket
-  unsigned spill_raw = 0, far_raw = 0, fmin = kNoBucket, need_l = 0;
-  for (int t = 0; t < T; ++t) {
-    const unsigned sr = ld_dev(&c->tq[t].spill_tail[so].v);
-    const unsigned fr = ld_dev(&c->tq[t].far_tail[far_in].v);
-    const unsigned fm = ld_dev(&c->tq[t].far_min[far_in].v);  // (read whether or not the list is empty)
-    spill_raw += sr;
-    far_raw += fr;
-    need_l = sr > need_l ? sr : need_l;
-    need_l = fr > need_l ? fr : need_l;
-    if (fr) fmin = fm < fmin ? fm : fmin;
-  }
+  // the pending spill and far lists: fill, smallest far bucket
+  const unsigned spill_raw = ld_dev(&tq.spill_tail[so].v);
+  const unsigned far_raw = ld_dev(&tq.far_tail[far_in].v);
+  const unsigned fm = ld_dev(&tq.far_min[far_in].v);  // (read whether or not the list is empty)
+  const unsigned fmin = far_raw ? fm : kNoBucket;
+  const unsigned need_l = spill_raw > far_raw ? spill_raw : far_raw;
   unsigned hout = 0, heavy_raw = 0;
   if constexpr (W::kSplit) {
     hout = (unsigned)snap.hout;
     heavy_raw = ld_dev(&c->heavy_tail[hout].v);
   }
-  // window occupancy, lane j looks at bucket cur + j in every team
-  unsigned wraw = 0, wmax = 0;
+  // window occupancy, lane j looks at bucket cur + j
+  unsigned wraw = 0;
   bool nonempty = false;
   if (lane < K) {
     const unsigned slot = (cur + (unsigned)lane) & (unsigned)(K - 1);
     const bool consumed = in_kind == kInWin && (int)slot == in_index;
-    if (!consumed)
-      for (int t = 0; t < T; ++t) {
-        const unsigned x = ld_dev(&c->tq[t].win_tail[slot].v);
-        wraw += x;
-        wmax = x > wmax ? x : wmax;
-      }
+    if (!consumed) wraw = ld_dev(&tq.win_tail[slot].v);
     const unsigned bk = cur + (unsigned)lane;
     nonempty = wraw > 0 && bk >= cur && bk < win_hi;
   }
-  unsigned long long need_w = wmax;
+  unsigned long long need_w = wraw;
   for (int o = 32; o >= 1; o >>= 1) {
     unsigned long long y = __shfl_xor(need_w, o);
     need_w = need_w > y ? need_w : y;
   }
-  // largest current distance among the targets (INF while one is unreached)
+  // largest current distance among the team's targets (INF while one is
+  // unreached)
   unsigned tmax = 0;
   if (a.tgts)
-    for (int q = lane; q < a.reps; q += kWave) {
+    for (int q = t0 + lane * T; q < a.reps; q += kWave * T) {
       const unsigned dt = (unsigned)__hip_atomic_load(&a.dist[a.tgts[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       tmax = dt > tmax ? dt : tmax;
     }
@@ -1857,74 +1867,69 @@ __device__ void decide(const Args& a, const S& snap) {
   }
   const unsigned slot_cur_cnt = __shfl(wraw, 0);
   const unsigned long long ne = __ballot(nonempty) & ~1ull;  // buckets after cur
-  // The consumed input list's chunks, in every team, go back to the pool
-  // (every lane takes a share of each chunk table).  After a failure the
-  // call ends and the pool is rebuilt by the next one.
+  // The consumed input list's chunks go back to the team's stack (every
+  // lane takes a share of the chunk table).  After a failure the call ends
+  // and the pool is rebuilt by the next one.
   if (!(W::kSplit && in_kind == kInHeavy)) {
-    int top = (int)ld_dev(&c->free_top.v);
+    const unsigned lo = team_lo(a.pool_chunks, T, t0);
+    const unsigned size = team_lo(a.pool_chunks, T, t0 + 1) - lo;
+    int top = (int)ld_dev(&c->free_top[t0].v);
     if (lane == 0) {
-      const unsigned taken = (unsigned)((int)a.pool_chunks - top);
-      if (taken > ld_dev(&c->pool_peak.v)) st_dev(&c->pool_peak.v, taken);
+      const unsigned taken = (unsigned)((int)size - top);
+      if (taken > ld_dev(&c->pool_peak[t0].v)) st_dev(&c->pool_peak[t0].v, taken);
     }
-    for (int t = 0; t < T && status == 0; ++t) {
+    if (status == 0) {
       // the list's fill is the team's input size of this round (it takes no
       // entries while it is the input)
-      const unsigned used = T == 1 ? snap.in_count : ld_dev(&c->tq[t].in_count.v);
+      const unsigned used = snap.in_count;
       const unsigned nch = (used + kChunk - 1) >> kChunkLog;
-      unsigned* tab = chunk_slot(a, list_of(a, t, in_kind, in_index), 0);
-      bool bad = top < 0 || (unsigned)top + nch > a.pool_chunks;
+      unsigned* tab = chunk_slot(a, list_of(a, t0, in_kind, in_index), 0);
+      bool bad = top < 0 || (unsigned)top + nch > size;
       for (unsigned j = (unsigned)lane; j < nch && !bad; j += kWave) {
         const int ch = (int)ld_dev(tab + j);
-        if (ch < 0 || (unsigned)ch >= a.pool_chunks) {
+        if (ch < (int)lo || ch >= (int)(lo + size)) {
           bad = true;
         } else {
-          st_dev(reinterpret_cast<unsigned*>(a.fstack) + top + j, (unsigned)ch);
+          st_dev(reinterpret_cast<unsigned*>(a.fstack) + lo + top + j, (unsigned)ch);
           st_dev(tab + j, (unsigned)kNoChunk);
         }
       }
       if (__ballot(bad)) {
         status = OG_ERR_INTERNAL;  // a chunk table disagrees with its list's fill
         if (lane == 0) set_status(c, status);
-      } else {
-        top += (int)nch;
+      } else if (lane == 0) {
+        st_dev(&c->free_top[t0].v, (unsigned)(top + (int)nch));
       }
     }
-    if (status == 0 && lane == 0) st_dev(&c->free_top.v, (unsigned)top);
   }
   if (lane != 0) return;
-  // the consumed input list is empty again, in every team
-  for (int t = 0; t < T; ++t) {
-    TeamQ& q = c->tq[t];
-    if (in_kind == kInWin) st_dev(&q.win_tail[in_index].v, 0);
-    else if (in_kind == kInSpill) st_dev(&q.spill_tail[in_index].v, 0);
-    else if (!(W::kSplit && in_kind == kInHeavy)) {
-      st_dev(&q.far_tail[in_index].v, 0);
-      st_dev(&q.far_min[in_index].v, kNoBucket);
-    }
-    st_dev(&q.in_head.v, 0);
+  // the consumed input list is empty again
+  if (in_kind == kInWin) st_dev(&tq.win_tail[in_index].v, 0);
+  else if (in_kind == kInSpill) st_dev(&tq.spill_tail[in_index].v, 0);
+  else if (!(W::kSplit && in_kind == kInHeavy)) {
+    st_dev(&tq.far_tail[in_index].v, 0);
+    st_dev(&tq.far_min[in_index].v, kNoBucket);
   }
+  st_dev(&tq.in_head.v, 0);
   if (W::kSplit && in_kind == kInHeavy) st_dev(&c->heavy_tail[in_index].v, 0);
   st_dev(&c->buf_tail.v, 0);
   // a consumed far list hands its role to the other one (next generation;
   // the snapshot's far_stamp is the generation plus that one)
-  st_dev(&c->c.far_gen, snap.far_stamp);
+  st_dev(&tc.far_gen, snap.far_stamp);
   {
-    const unsigned rm = __hip_atomic_exchange(&c->round_max_batches.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicAdd(&c->st[kStChain].v, (unsigned long long)rm);
+    const unsigned rm = __hip_atomic_exchange(&c->round_max_batches[t0].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicAdd(&c->chain[t0].v, (unsigned long long)rm);
+  }
+  {
+    const unsigned long long nd = need_w > need_l ? need_w : need_l;
+    __hip_atomic_fetch_max(&c->need.v, nd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
-  unsigned long long need = __hip_atomic_load(&c->need.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (need_w > need) need = need_w;
-  if (need_l > need) need = need_l;
-  __hip_atomic_store(&c->need.v, need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
-  // (count: the one team's input size; more teams read theirs below)
   auto clampcap = [&](unsigned x) { return x < a.cap ? x : a.cap; };
   unsigned done = 0;
-  unsigned ncur = cur, count = 0, buckets = ld_dev(&c->c.buckets), nwin_hi = win_hi;
+  unsigned ncur = cur, count = 0, buckets = ld_dev(&tc.buckets), nwin_hi = win_hi;
   int nkind = kInWin, nindex = 0, nspill_out = so;
   unsigned nhout = hout;
-  bool heavy_next = false;
   if (status != 0) {
     done = 1;
   } else if (a.max_rounds && round >= a.max_rounds) {
@@ -1950,7 +1955,6 @@ __device__ void decide(const Args& a, const S& snap) {
     nkind = kInHeavy;
     nindex = (int)hout;
     nhout = 1u - hout;
-    heavy_next = true;
     count = heavy_raw < a.hcap ? heavy_raw : a.hcap;
   } else {
     const unsigned wnext = ne ? cur + (unsigned)(__ffsll((long long)ne) - 1) : kNoBucket;
@@ -1970,51 +1974,32 @@ __device__ void decide(const Args& a, const S& snap) {
       } else {
         nkind = kInWin;
         nindex = (int)(next & (unsigned)(K - 1));
-        if (T == 1) count = clampcap(ld_dev(&c->tq[0].win_tail[nindex].v));
+        count = clampcap(ld_dev(&tq.win_tail[nindex].v));
       }
       nwin_hi = sat_add(next, (unsigned)K);
     }
   }
-  // each team's share of the next round's input (a heavy list is shared:
-  // the split instantiation runs one team)
-  unsigned total = count;
-  if (T == 1) {
-    st_dev(&c->tq[0].in_count.v, done ? 0u : count);
-  } else {
-    total = 0;
-    for (int t = 0; t < T; ++t) {
-      unsigned cnt = 0;
-      if (!done && !heavy_next) {
-        const TeamQ& q = c->tq[t];
-        cnt = clampcap(nkind == kInFar ? ld_dev(&q.far_tail[nindex].v)
-                     : nkind == kInSpill ? ld_dev(&q.spill_tail[nindex].v)
-                                         : ld_dev(&q.win_tail[nindex].v));
-      } else if (heavy_next) {
-        cnt = count;
-      }
-      st_dev(&c->tq[t].in_count.v, cnt);
-      total += cnt;
-    }
-  }
-  st_dev(&c->c.cur, ncur);
-  st_dev(&c->c.in_kind, (unsigned)nkind);
-  st_dev(&c->c.in_index, (unsigned)nindex);
-  st_dev(&c->c.spill_out, (unsigned)nspill_out);
-  st_dev(&c->c.far_in, (unsigned)far_in);
-  st_dev(&c->c.win_hi, nwin_hi);
-  st_dev(&c->c.buckets, buckets);
+  st_dev(&tq.in_count.v, done ? 0u : count);
+  st_dev(&tc.cur, ncur);
+  st_dev(&tc.in_kind, (unsigned)nkind);
+  st_dev(&tc.in_index, (unsigned)nindex);
+  st_dev(&tc.spill_out, (unsigned)nspill_out);
+  st_dev(&tc.far_in, (unsigned)far_in);
+  st_dev(&tc.win_hi, nwin_hi);
+  st_dev(&tc.buckets, buckets);
   if constexpr (W::kSplit) {
-    if (nhout != hout) st_dev(&c->c.hgen, snap.hgen + 1u);
-    st_dev(&c->c.hout, nhout);
+    if (nhout != hout) st_dev(&tc.hgen, snap.hgen + 1u);
+    st_dev(&tc.hout, nhout);
   }
-  if constexpr (W::kPull) st_dev(&c->c.pull, done ? 0u : pull_round(a, total));
+  if constexpr (W::kPull) st_dev(&tc.pull, done ? 0u : pull_round(a, count));
   if constexpr (W::kBlocks) {
     st_dev(&c->blk_out.v, (unsigned)a.nwg);  // one input-scan token per workgroup
     st_dev(&c->blk_head.v, 0u);              // ring positions restart
     st_dev(&c->blk_tail.v, 0u);
   }
-  st_dev(&c->c.done, done);
-  st_dev(&c->c.round, round);
+  st_dev(&tc.done, done);
+  st_dev(&tc.round, round);
+  if (done) atomicSub(&c->live.v, 1u);  // (a team decides done once: its workgroups stop)
 }
 
 // The workgroup's team (thread 0, once at the start of a kernel).
@@ -2028,33 +2013,36 @@ __device__ void init_team(const Args& a, S& s) {
 template <class W, class S>
 __device__ void load_control(const Args& a, S& s) {
   Ctl* c = a.ctl;
-  s.cur = ld_dev(&c->c.cur);
-  s.in_kind = (int)ld_dev(&c->c.in_kind);
-  s.in_index = (int)ld_dev(&c->c.in_index);
+  const Control& tc = c->tc[s.team];
+  s.cur = ld_dev(&tc.cur);
+  s.in_kind = (int)ld_dev(&tc.in_kind);
+  s.in_index = (int)ld_dev(&tc.in_index);
   s.in_count = ld_dev(&c->tq[s.team].in_count.v);
-  s.win_hi = ld_dev(&c->c.win_hi);
-  s.spill_out = (int)ld_dev(&c->c.spill_out);
-  s.round = ld_dev(&c->c.round);
-  const int far_in = (int)ld_dev(&c->c.far_in);
+  s.win_hi = ld_dev(&tc.win_hi);
+  s.spill_out = (int)ld_dev(&tc.spill_out);
+  s.round = ld_dev(&tc.round);
+  const int far_in = (int)ld_dev(&tc.far_in);
   s.far_out = s.in_kind == kInFar ? 1 - far_in : far_in;
-  s.far_stamp = ld_dev(&c->c.far_gen) + (s.in_kind == kInFar ? 1u : 0u);
-  s.epoch = ld_dev(&c->c.epoch);
+  s.far_stamp = ld_dev(&tc.far_gen) + (s.in_kind == kInFar ? 1u : 0u);
+  s.epoch = ld_dev(&tc.epoch);
   if constexpr (W::kSplit) {
-    s.hout = (int)ld_dev(&c->c.hout);
-    s.hgen = ld_dev(&c->c.hgen);
+    s.hout = (int)ld_dev(&tc.hout);
+    s.hgen = ld_dev(&tc.hgen);
   }
-  if constexpr (W::kPull) s.pull = (int)ld_dev(&c->c.pull);
-  s.done = ld_dev(&c->c.done) || ld_dev(&c->status.v) != 0;
+  if constexpr (W::kPull) s.pull = (int)ld_dev(&tc.pull);
+  s.done = ld_dev(&tc.done) || ld_dev(&c->status.v) != 0;
 }
 
-// Device-wide synchronisation.  Every wavefront waits for its own stores
-// and atomics to complete; thread 0 of each workgroup then arrives on its
-// group's counter (kGroup workgroups per counter, each on its own cache
-// line), the last of a group arrives on the root counter, and the last
-// workgroup overall (with decide_next: after taking the bucket decision with
-// wave 0) publishes the new barrier count on kFlags release flags.  With
-// wait_others (the persistent engine) every other workgroup spins on one of
-// those flags; the host-driven engine ends the kernel instead.
+// Synchronisation of a team's workgroups (device-wide when one team runs).
+// Every wavefront waits for its own stores and atomics to complete; thread 0
+// of each workgroup then arrives on its group's counter (kGroup workgroups
+// of the team per counter, each on its own cache line), the last of a group
+// arrives on the team's root counter, and the team's last workgroup (with
+// decide_next: after taking the team's bucket decision with wave 0)
+// publishes the team's new barrier count on its kFlags / teams release
+// flags.  With wait_others (the persistent engine) every other workgroup of
+// the team spins on one of those flags; the host-driven engine ends the
+// kernel instead.
 __device__ void flush_counters(const Args& a, Counters& c);
 
 template <class W, class S>
@@ -2063,21 +2051,24 @@ __device__ void round_barrier(const Args& a, S& s, Counters& c, bool wait_others
   // a wavefront whose 32-bit counts near 2^31 adds them to the totals now
   if (__ballot((c.relax | c.improve | c.push_local | c.push_global | c.far | c.batches) >= 0x80000000u))
     flush_counters(a, c);
-  if (threadIdx.x == 0) atomicMax(&ctl->round_max_batches.v, c.round_batches);
+  if (threadIdx.x == 0) atomicMax(&ctl->round_max_batches[s.team].v, c.round_batches);
   c.round_batches = 0;
   wait_vm();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int grp = (int)blockIdx.x / kGroup;
-    const int ngrp = (a.nwg + kGroup - 1) / kGroup;
-    const int gsize = grp == ngrp - 1 ? a.nwg - grp * kGroup : kGroup;
+    // the team's groups: counters team * gstride .. team * gstride + ngrp - 1
+    const int gstride = ((a.nwg + a.teams - 1) / a.teams + kGroup - 1) / kGroup;
+    const int g = s.team_rank / kGroup;
+    const int ngrp = (s.team_size + kGroup - 1) / kGroup;
+    const int gsize = g == ngrp - 1 ? s.team_size - g * kGroup : kGroup;
+    const int grp = s.team * gstride + g;
     bool last = false;
     const unsigned p = atomicAdd(&ctl->bar_grp[grp].v, 1u);
     if (p == (unsigned)gsize - 1) {
       (void)atomicExch(&ctl->bar_grp[grp].v, 0u);
-      const unsigned q = atomicAdd(&ctl->bar_root.v, 1u);
+      const unsigned q = atomicAdd(&ctl->bar_root[s.team].v, 1u);
       if (q == (unsigned)ngrp - 1) {
-        (void)atomicExch(&ctl->bar_root.v, 0u);
+        (void)atomicExch(&ctl->bar_root[s.team].v, 0u);
         last = true;
       }
     }
@@ -2085,15 +2076,16 @@ __device__ void round_barrier(const Args& a, S& s, Counters& c, bool wait_others
   }
   __syncthreads();
   const unsigned next = s.epoch + 1;
+  const int fpt = kFlags / a.teams;  // release flags per team
   if (s.last) {
     if (threadIdx.x < kWave) {
       if (decide_next) decide<W>(a, s);
-      if (threadIdx.x == 0) st_dev(&ctl->c.epoch, next);
+      if (threadIdx.x == 0) st_dev(&ctl->tc[s.team].epoch, next);
       wait_vm();
-      st_dev(&ctl->flag[threadIdx.x].v, next);
+      if ((int)threadIdx.x < fpt) st_dev(&ctl->flag[s.team * fpt + (int)threadIdx.x].v, next);
     }
   } else if (wait_others && threadIdx.x == 0) {
-    const unsigned* f = &ctl->flag[blockIdx.x % kFlags].v;
+    const unsigned* f = &ctl->flag[s.team * fpt + s.team_rank % fpt].v;
     while (ld_dev(f) < next) __builtin_amdgcn_s_sleep(2);
   }
   __syncthreads();
@@ -2264,8 +2256,9 @@ __global__ __launch_bounds__(kBlock) void k_init_core(Args a) {
 
 // The queue pool at the start of a call: every chunk table entry empty but
 // team 0's far list 0's first `pre` (chunks 0 .. pre-1, where a single
-// team's sources or, for k-core, all vertices are filed), the other chunks
-// on the free stack.  Runs after the control block is zeroed.
+// team's sources or, for k-core, all vertices are filed; pre is 0 when more
+// teams run), each team's other chunks on its stack.  Runs after the
+// control block is zeroed.
 __global__ __launch_bounds__(kBlock) void k_pool_init(Args a, unsigned pre) {
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
   const unsigned long long ntab = (unsigned long long)a.teams * (a.K + 4) * a.tchunks;
@@ -2274,40 +2267,58 @@ __global__ __launch_bounds__(kBlock) void k_pool_init(Args a, unsigned pre) {
     const unsigned j = (unsigned)(i % a.tchunks);
     a.ctab[i] = (int)(i / a.tchunks) == far0 && j < pre ? (int)j : kNoChunk;
   }
-  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.pool_chunks - pre;
-       i += stride)
-    a.fstack[i] = (int)(pre + i);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctl->free_top.v = a.pool_chunks - pre;
-    a.ctl->pool_peak.v = pre;
+  // team t's stack, at positions lo .. hi-1, lists its chunks lo .. hi-1
+  // (team 0's after the first pre)
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.pool_chunks;
+       i += stride) {
+    int t = (int)((i * (unsigned long long)a.teams) / a.pool_chunks);
+    while (t + 1 < a.teams && team_lo(a.pool_chunks, a.teams, t + 1) <= i) ++t;
+    while (t > 0 && team_lo(a.pool_chunks, a.teams, t) > i) --t;
+    const unsigned lo = team_lo(a.pool_chunks, a.teams, t);
+    const unsigned skip = t == 0 ? pre : 0u;
+    const unsigned size = team_lo(a.pool_chunks, a.teams, t + 1) - lo;
+    const unsigned j = (unsigned)i - lo;
+    if (j + skip < size) a.fstack[i] = (int)(lo + skip + j);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (unsigned)a.teams) {
+    const int t = (int)threadIdx.x;
+    const unsigned size = team_lo(a.pool_chunks, a.teams, t + 1) - team_lo(a.pool_chunks, a.teams, t);
+    const unsigned skip = t == 0 ? pre : 0u;
+    a.ctl->free_top[t].v = size - skip;
+    a.ctl->pool_peak[t].v = skip;
   }
 }
 
 __global__ void k_init_ctl(Args a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Ctl* c = a.ctl;
-  unsigned b0 = kNoBucket, most = 0;
+  unsigned most = 0;
   if (a.teams == 1) c->tq[0].far_tail[0].v = (unsigned)a.nsrc;  // (more teams: counted by k_init_sources)
   for (int t = 0; t < a.teams; ++t) {
     TeamQ& q = c->tq[t];
-    b0 = q.far_min[0].v < b0 ? q.far_min[0].v : b0;
     q.in_count.v = q.far_tail[0].v;
     most = q.far_tail[0].v > most ? q.far_tail[0].v : most;
     q.far_min[1].v = kNoBucket;
   }
-  c->c.cur = b0;
-  c->c.in_kind = kInFar;
-  c->c.in_index = 0;
-  c->c.far_in = 0;
-  c->c.win_hi = sat_add(b0, (unsigned)a.K);
-  c->c.buckets = 1;
+  for (int t = 0; t < a.teams; ++t) {
+    const unsigned b = c->tq[t].far_min[0].v;
+    Control& tc = c->tc[t];
+    tc.cur = b;
+    tc.in_kind = kInFar;
+    tc.in_index = 0;
+    tc.far_in = 0;
+    tc.win_hi = sat_add(b, (unsigned)a.K);
+    tc.buckets = 1;
+  }
+  c->live.v = (unsigned)a.teams;
+  c->teams.v = (unsigned)a.teams;
   c->need.v = most;
   c->blk_out.v = (unsigned)a.nwg;  // vertex blocks: one input-scan token per workgroup
 }
 
 // Pull instantiations: the direction of the first round.
 __global__ void k_init_pull(Args a) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctl->c.pull = pull_round(a, a.ctl->tq[0].in_count.v);
+  if (threadIdx.x == 0 && blockIdx.x == 0) a.ctl->tc[0].pull = pull_round(a, a.ctl->tq[0].in_count.v);
 }
 
 // Pull instantiations: the slices of every row longer than kLongRow, as
@@ -3717,14 +3728,14 @@ size_t table_bytes(const Shape& sh) {
 
 // Teams a call may split its workgroups into (its workspace holds their
 // lists): a batched launch of the eager push engine, schedule.teams (0 =
-// 2 from 8 queries on, 4 from 32: the fastest on the road grid, where 8
-// teams of one XCD each leave too few workgroups per query), at most one
-// per query; any other call one.  The launch runs min(that, workgroups).
+// one per query up to 8, one per XCD: each team runs rounds of its own, the
+// fastest on the road grid), at most one per query; any other call one.
+// The launch runs min(that, workgroups).
 int team_cap(const og_schedule* r, const Shape& sh) {
   if (sh.core || sh.reps < 2 || r->update == OG_LAZY_UPDATE) return 1;
   if (r->flags & (OG_FLAG_LIGHT_HEAVY | OG_FLAG_DENSE_PULL | OG_FLAG_HYBRID_DIRECTION | OG_FLAG_VERTEX_BLOCKS))
     return 1;
-  int t = r->teams > 0 ? r->teams : (sh.reps >= 32 ? 4 : sh.reps >= 8 ? 2 : 1);
+  int t = r->teams > 0 ? r->teams : kMaxTeams;
   if (t > kMaxTeams) t = kMaxTeams;
   if (t > sh.reps) t = sh.reps;
   return t;
@@ -3737,7 +3748,7 @@ int team_cap(const og_schedule* r, const Shape& sh) {
 // takes its chunk through the usual hand-over.  Pool size: schedule.queue_pool entries rounded up to whole
 // chunks, by default twice one list's capacity plus one chunk per list (the
 // partly filled last chunks), never more than every list full at once, and
-// never fewer than the sources' chunks plus one.
+// never fewer than the sources' chunks plus one, nor than one chunk per team.
 struct PoolLayout {
   unsigned tchunks, chunks, pre;
   size_t ctab, fstack, pool, end;
@@ -3752,6 +3763,7 @@ PoolLayout pool_layout(const og_schedule* r, const Shape& sh, long long cap, int
   long long ch = r->queue_pool > 0 ? (r->queue_pool + ck - 1) / ck : (2 * cap + ck - 1) / ck + lists;
   if (ch > lists * (long long)L.tchunks) ch = lists * (long long)L.tchunks;
   if (ch < (long long)L.pre + 1) ch = (long long)L.pre + 1;
+  if (ch < teams) ch = teams;  // a chunk for every team's share
   L.chunks = (unsigned)ch;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -3893,8 +3905,20 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   if (!st) return;
   st->status = (og_status)h.status.v;
   st->workgroups = nwg;
-  st->rounds = h.c.round;
-  st->buckets = h.c.buckets;
+  // teams run rounds of their own: the rounds, barriers and critical path of
+  // the team that took the most, the buckets of all teams, and the pool a
+  // split into equal team shares needs
+  const int T = h.teams.v >= 1 && h.teams.v <= (unsigned)kMaxTeams ? (int)h.teams.v : 1;
+  int64_t rounds = 0, buckets = 0, barriers = 0, chain = 0, peak = 0;
+  for (int t = 0; t < T; ++t) {
+    rounds = std::max<int64_t>(rounds, h.tc[t].round);
+    buckets += h.tc[t].buckets;
+    barriers = std::max<int64_t>(barriers, h.tc[t].epoch);
+    chain = std::max<int64_t>(chain, (int64_t)h.chain[t].v);
+    peak = std::max<int64_t>(peak, h.pool_peak[t].v);
+  }
+  st->rounds = rounds;
+  st->buckets = buckets;
   st->relaxations = (int64_t)h.st[kStRelax].v;
   st->improvements = (int64_t)h.st[kStImprove].v;
   st->pushes_local = (int64_t)h.st[kStPushLocal].v;
@@ -3903,10 +3927,10 @@ void fill_stats(const Ctl& h, og_stats* st, int nwg) {
   st->reached_vertices = (int64_t)h.st[kStReachedV].v;
   st->reached_edges = (int64_t)h.st[kStReachedE].v;
   st->queue_needed = (int64_t)h.need.v;
-  st->pool_needed = (int64_t)h.pool_peak.v * kChunk;
+  st->pool_needed = peak * T * kChunk;
   st->batches = (int64_t)h.st[kStBatches].v;
-  st->chain = (int64_t)h.st[kStChain].v;
-  st->barriers = (int64_t)h.c.epoch;
+  st->chain = chain;
+  st->barriers = barriers;
 }
 
 // Executable hipGraph of `group` host-driven rounds (two kernels per lazy
@@ -4384,12 +4408,12 @@ og_status run(const og_graph* g, const Shape& sh, const std::vector<int>& vsrcs,
           for (int ph = 0; ph < phases; ++ph) hipLaunchKernelGGL(k_round<W>, dim3(nwg), dim3(kBlock), 0, stream, a, ph);
       }
       launched += group;
-      unsigned hd[64];  // the Control line and the status line
-      if (hipMemcpyAsync(hd, a.ctl, sizeof(hd), hipMemcpyDeviceToHost, stream) != hipSuccess)
+      Word hd[2];  // the status line and the live-teams line
+      static_assert(offsetof(Ctl, live) == offsetof(Ctl, status) + sizeof(Word), "status and live adjacent");
+      if (hipMemcpyAsync(hd, &a.ctl->status, sizeof(hd), hipMemcpyDeviceToHost, stream) != hipSuccess)
         return fail(OG_ERR_HIP);
       if (hipStreamSynchronize(stream) != hipSuccess) return fail(OG_ERR_HIP);
-      const Ctl* hv = reinterpret_cast<const Ctl*>(hd);
-      done = hv->c.done || hv->status.v;
+      done = hd[1].v == 0 || hd[0].v;
     }
   }
   if (timing) (void)hipEventRecord(t_timers.ev[2], stream);

@@ -65,20 +65,21 @@ def _fake_graph(n=10, m=20):
     return _lib.OgGraph(n, m, 0x1000, 0x2000, 0x3000)
 
 
-CTL = 131072  # the control block: counters, flags and each team's queue tails
+CTL = 131072  # the control block: counters, flags, each team's control state and queue tails
 
 
 def _queues(cap, k, nsrc=1, pool=0, teams=1):
     """Bytes of the global queues: per-queue chunk tables (K + 4 queues per
     team), the free stack and the pool of 4,096-entry chunks (default: twice
     one queue's capacity plus one chunk per queue, at most every queue full,
-    at least the sources' chunks plus one), each region 256-byte aligned."""
+    at least the sources' chunks plus one and one chunk per team), each
+    region 256-byte aligned."""
     ck = 4096
     lists = teams * (k + 4)
     tch = -(-cap // ck)
     pre = -(-nsrc // ck)
     ch = -(-pool // ck) if pool > 0 else -(-2 * cap // ck) + lists
-    ch = max(min(ch, lists * tch), pre + 1)
+    ch = max(min(ch, lists * tch), pre + 1, teams)
 
     def v(nbytes):
         return (nbytes + 255) // 256 * 256
@@ -140,14 +141,13 @@ def test_workspace_bytes():
 
 def test_batch_workspace_holds_every_teams_queues():
     """A batched call of the eager push engine sizes its queues for its teams
-    (schedule.teams; by default 2 from 8 queries, 4 from 32; at most 8 and
-    one per query); the lazy update and the split, pull and block variants
-    keep one team."""
+    (schedule.teams; by default 8; at most 8 and one per query); the lazy
+    update and the split, pull and block variants keep one team."""
     lib = _lib.load()
     g = _fake_graph(1000, 4000)
     table = lambda nq: (4 * (nq + nq) + 255) // 256 * 256  # sources and targets
     per = 1000 + 4000 // 8
-    for nq, teams, want in ((8, 0, 2), (3, 0, 1), (16, 0, 2), (32, 0, 4), (64, 0, 4), (8, 1, 1), (8, 4, 4),
+    for nq, teams, want in ((8, 0, 8), (3, 0, 3), (7, 0, 7), (16, 0, 8), (64, 0, 8), (8, 1, 1), (8, 4, 4),
                             (8, 99, 8), (3, 8, 3)):
         s = og.Schedule(delta=4, window_buckets=8, teams=teams).to_c()
         got = lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(s), nq)
