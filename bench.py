@@ -5,7 +5,7 @@ edges; each grid edge kept with p = 0.75, 0.1 % long-range edges within 64
 grid steps, weights llround(10 * length * U(1, 2))), seed 0; 8 sources drawn
 with seed 1.  One step = the whole workload through the C ABI: all 8
 sources in one og_sssp_batch launch (initialisation, the bucket engine over
-all rounds, fused, Delta 1024, degree-binned load balancing, and the
+all rounds, fused, Delta 256, degree-binned load balancing, and the
 canonical predecessor pass of every query), with the graph already resident
 in HBM.  The same sources one query per launch (Delta 512) are reported
 beside it as the serial figure.
@@ -474,8 +474,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=4096)
-    ap.add_argument("--delta", type=int, default=1024,
-                    help="bucket width of the headline's batched launch (1024: the fastest of its 2^8..2^14 "
+    ap.add_argument("--delta", type=int, default=256,
+                    help="bucket width of the headline's batched launch (256: the fastest of its 2^8..2^14 "
                          "sweep on this graph, which every run repeats); 0 = run at the sweep's fastest")
     ap.add_argument("--serial-delta", type=int, default=512,
                     help="bucket width of the one-query-per-launch legs (512: the fastest of their sweep); "

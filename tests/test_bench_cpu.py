@@ -37,10 +37,10 @@ def test_engine_hash_ignores_comments_only():
 
 def test_committed_profile_is_current():
     """The committed traffic summaries were taken on the committed engine:
-    the headline's batched launch of 8 queries at Delta 1024, and one query
+    the headline's batched launch of 8 queries at Delta 256, and one query
     per launch at Delta 512."""
     assert os.path.exists(bench.TRAFFIC_FILE) and os.path.exists(bench.BATCH_TRAFFIC_FILE)
-    assert bench.read_traffic(1024, 8) is not None
+    assert bench.read_traffic(256, 8) is not None
     assert bench.read_traffic(512) is not None
 
 
@@ -49,7 +49,7 @@ def test_kernel_profiles_are_current():
     current engine were taken on it (a code change without retaking them
     fails here); the older stall counters say which code they were taken on."""
     current = ["k_persistent_road4096_traffic.txt", "kernels_road4096_d512_fused.txt",
-               "k_persistent_road4096_batch8_traffic.txt", "kernels_road4096_batch8_d1024.txt",
+               "k_persistent_road4096_batch8_traffic.txt", "kernels_road4096_batch8_d256.txt",
                "k_persistent_road4096_batch8_counters.txt",
                "kernels_road4096_blocks_d2048.txt", "k_persistent_road4096_bins_counters.txt",
                "kernels_kcore_rmat24_lazy.txt", "kernels_sssp_rmat24_d32_unfused.txt",

@@ -1,7 +1,8 @@
 """Batched launches split into teams of workgroups (workgroup b serves team
 b % teams, query q belongs to team q % teams, each team with its own bucket
-lists): every team count, load balancing, update, engine and grid size
-gives the oracle's distances and canonical predecessors for every query.
+lists, pool share and rounds): every team count, load balancing, update,
+engine and grid size gives the oracle's distances and canonical
+predecessors for every query, also when teams finish at different times.
 
 Graphs: the 128 x 128 road-like grid (seed 3) and R-MAT scale 12.
 """
@@ -144,3 +145,38 @@ def test_teams_exhausted_pool(orc, rmat12):
     torch.cuda.synchronize()
     assert st["status"] == 0
     check_all(orc, g, srcs, d, p, "after exhaustion")
+
+
+def test_teams_finishing_at_different_times(orc, road128):
+    """Eight teams of one query each, where team 0's source is isolated (its
+    team is done after one round) and team 1's source lies in the main grid:
+    the finished team's workgroups leave while the others run on."""
+    g, dg = road128
+    iso = int(np.where(g.degrees() == 0)[0][0])
+    srcs = [iso] + [int(s) for s in gg.pick_sources(g, 7, seed=39)]
+    tag = f"road128 nq=8 teams=8, query 0 from isolated vertex {iso}"
+    say(tag)
+    d, p, st = og.sssp_batch(dg, srcs, og.Schedule(delta=64, teams=8, flags=og.OG_FLAG_DEGREE_BINS))
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    check_all(orc, g, srcs, d, p, tag)
+    # the rounds and barriers of the team that took the most (one barrier per
+    # eager round)
+    assert st["rounds"] >= 2 and st["barriers"] == st["rounds"]
+
+
+@pytest.mark.parametrize("engine", [og.OG_ENGINE_PERSISTENT, og.OG_ENGINE_HOST_ROUNDS])
+def test_teams_stop_early_on_their_own_targets(orc, road128, engine):
+    """Point-to-point queries, one team each: team 0's target is its source
+    (settled at the first decision), the others' targets are far away."""
+    g, dg = road128
+    srcs = [int(s) for s in gg.pick_sources(g, 8, seed=40)]
+    dsts = [srcs[0]] + [int(t) for t in gg.pick_sources(g, 7, seed=41)]
+    say(f"road128 ppsp_batch nq=8 teams=8 engine={engine}, query 0 target = source")
+    d, p, st = og.ppsp_batch(dg, srcs, dsts, og.Schedule(delta=64, teams=8, engine=engine))
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    got = d[torch.arange(8, device=DEV), torch.as_tensor(dsts, device=DEV)].cpu().numpy()
+    want = np.array([orc.ppsp(g, int(s), int(t)) for s, t in zip(srcs, dsts)])
+    want = np.where(want < 0, og.INF, want)
+    assert got[0] == 0 and np.array_equal(got, want)
