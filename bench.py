@@ -795,6 +795,8 @@ def main() -> int:
             "step": f"all {len(srcs)} sources in one og_sssp_batch launch (dist + pred of each); the same "
                     f"sources one query per launch are under 'serial'",
             "queries_per_launch": len(srcs),
+            "teams": f"{min(8, len(srcs))} teams of workgroups (the default: one per query, at most one per XCD), "
+                     f"each with its queries' bucket lists, pool share and rounds of its own",
             "n": g.n, "m": g.m, "delta": args.delta, "delta_sweep_engine_ms": bsweep,
             "serial_delta_sweep_engine_ms": sweep,
             "update": "eager_with_fusion", "engine": "persistent",

@@ -15,7 +15,9 @@ is
   3. Delta refined by factors of sqrt(2) around the best value;
   4. the workgroup count;
   5. degree-binned load balancing and its two cut-offs (lane and wavefront
-     bins; eager schedules).
+     bins; eager schedules);
+  6. for batched runners, the number of workgroup teams (each team serves
+     its own queries with rounds of its own).
 
 Each stage keeps the best candidate (lowest median engine time).  Results
 are returned as a `Schedule` plus a log of every candidate tried and can be
@@ -76,10 +78,11 @@ class Autotuner:
     points on sample sources.
     """
 
-    def __init__(self, runner, base: Schedule | None = None, repeats: int = 1):
+    def __init__(self, runner, base: Schedule | None = None, repeats: int = 1, batched: bool = False):
         self.runner = runner
         self.base = base or Schedule()
         self.repeats = repeats
+        self.batched = batched  # the runner launches several queries at once: the team count matters
         self.trials: list[Trial] = []
         self._cache: dict = {}
 
@@ -105,7 +108,7 @@ class Autotuner:
             _, _, st = sssp_batch(graph, sources, s, pred=False, ws=ws)
             return float(st["engine_ms"])
 
-        return cls(run, **kw)
+        return cls(run, batched=len(sources) > 1, **kw)
 
     @classmethod
     def for_ppsp_batch(cls, graph: DeviceGraph, sources, targets, h: torch.Tensor | None = None, **kw):
@@ -118,7 +121,7 @@ class Autotuner:
                 _, _, st = astar_batch(graph, sources, targets, h, s, pred=False, ws=ws)
             return float(st["engine_ms"])
 
-        return cls(run, **kw)
+        return cls(run, batched=len(sources) > 1, **kw)
 
     # ------------------------------------------------------------ search
     def measure(self, s: Schedule) -> float:
@@ -178,6 +181,11 @@ class Autotuner:
         if not best.flags & _DIRECTIONS:
             cands = [best] + [Schedule(**{**asdict(best), "flags": best.flags | OG_FLAG_DEGREE_BINS, "bin_thread": bt,
                                           "bin_wave": bw}) for bt in (2, 4) for bw in (16, 64, 256)]
+            best, best_ms = self._best(cands)
+        # teams of workgroups (batched launches of the eager engine; 0 = the
+        # library's default, one per query up to 8)
+        if self.batched and best.update != OG_LAZY_UPDATE:
+            cands = [best] + [Schedule(**{**asdict(best), "teams": t}) for t in (1, 2, 4, 8) if t != best.teams]
             best, best_ms = self._best(cands)
         best = Schedule(**{**asdict(best), "flags": (base.flags & ~_CHOSEN) | (best.flags & _CHOSEN)})
         return TuneResult(best=best, best_ms=best_ms, trials=list(self.trials), seconds=time.perf_counter() - t0)

@@ -101,3 +101,15 @@ def test_degree_bin_cutoffs():
     # bins that do not pay are left out
     res = Autotuner(cost).tune(weight_scale=15.0)
     assert not res.best.flags & OG_FLAG_DEGREE_BINS
+
+
+def test_team_count_for_batched_runners():
+    """A batched runner's search ends with the team count; a single-query
+    runner never varies it."""
+    def runner(s):
+        return cost(s) + {0: 0.3, 1: 1.0, 2: 0.6, 4: 0.0, 8: 0.2}[s.teams]
+    res = Autotuner(runner, batched=True).tune(weight_scale=15.0)
+    assert res.best.teams == 4
+    assert {t.schedule["teams"] for t in res.trials} == {0, 1, 2, 4, 8}
+    res = Autotuner(runner).tune(weight_scale=15.0)
+    assert res.best.teams == 0 and all(t.schedule["teams"] == 0 for t in res.trials)
