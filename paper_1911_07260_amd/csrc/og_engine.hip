@@ -18,7 +18,8 @@
 //     the next round, which redistributes it over all workgroups.
 //   - The global minimum-bucket selection (section 3.2, getGlobalMinBucket;
 //     section 5.2, cross-thread minimum) is done once per round by the last
-//     workgroup to arrive at the device-wide barrier.
+//     workgroup to arrive at the device-wide barrier (in a batched launch
+//     split into teams: by the last of the team, at the team's barrier).
 //   - Stale entries are never removed from queues: entries carry (v, d) and
 //     are skipped when d > dist[v] (insert without delete).
 //
@@ -27,8 +28,9 @@
 // base CSR shared by all copies.  A batch of single-source queries on one
 // graph is the disjoint union of q copies with one source each; a
 // multi-source query (one copy, several sources at distance 0) covers many
-// disjoint graphs stored as one block-diagonal CSR.  All queries share the
-// bucket sequence, so they advance together through the same rounds.
+// disjoint graphs stored as one block-diagonal CSR.  The queries of one team
+// of workgroups (below) share its bucket sequence and advance together
+// through its rounds; different teams run their rounds independently.
 //
 // The same round structure carries the other schedules and algorithms, each
 // as its own template instantiation so that adding one leaves the machine
@@ -85,12 +87,14 @@ constexpr int kMaxQueries = 1024;    // queries in one launch
 constexpr int kMaxBatch = 1 << 20;  // queries in one batch call (in launches of at most kMaxQueries)
 constexpr size_t kCtlBytes = 131072;
 // A batched launch splits its workgroups into teams: workgroup b serves team
-// b % teams, which owns the queries q with q % teams == team and a set of
-// bucket lists of its own.  The hardware deals consecutive workgroups to the
-// XCDs in turn, so with 8 teams each XCD's L2 holds the working set of its
-// own queries only.  Every vertex a team files belongs to one of its queries
-// (edges stay within a query's copy of the graph), so a team's lists, LDS
-// rings and pushes never mix teams.
+// b % teams, which owns the queries q with q % teams == team, a set of bucket
+// lists, a share of the queue pool and a control state of its own.  A team's
+// workgroups synchronise only with each other and the team takes its own
+// bucket decisions, so no team waits for another's rounds.  The hardware
+// deals consecutive workgroups to the XCDs in turn, so with 8 teams each
+// XCD's L2 holds the working set of its own queries only.  Every vertex a
+// team files belongs to one of its queries (edges stay within a query's copy
+// of the graph), so a team's lists, LDS rings and pushes never mix teams.
 constexpr int kMaxTeams = 8;
 // The global bucket lists (K window slots, 2 spill lists, 2 far lists) draw
 // fixed-size chunks from a pool, each team from an equal share of its own:
