@@ -152,6 +152,11 @@ def test_batch_workspace_holds_every_teams_queues():
         s = og.Schedule(delta=4, window_buckets=8, teams=teams).to_c()
         got = lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(s), nq)
         assert got == CTL + table(nq) + _queues(nq * per + nq, 8, nsrc=nq, teams=want), (nq, teams)
+    # a tiny pool still gives every team's share a chunk (8 chunks, not the
+    # sources' one plus one)
+    tiny = og.Schedule(delta=4, window_buckets=8, teams=8, queue_pool=1).to_c()
+    assert lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(tiny), 8) == (
+        CTL + table(8) + _queues(8 * per + 8, 8, nsrc=8, pool=1, teams=8))
     lazy = og.Schedule(delta=4, window_buckets=8, update=og.OG_LAZY_UPDATE).to_c()
     vec = (8 * 1000 * 4 + 255) // 256 * 256
     assert lib.og_workspace_bytes_batch(ctypes.byref(g), ctypes.byref(lazy), 8) == (
