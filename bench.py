@@ -694,9 +694,9 @@ def main() -> int:
         bsrcs = bsrcs_all[:nq]
         bws = og.Workspace(dev)
 
-        def batch_leg(name, srcs_b, fl):
+        def batch_leg(name, srcs_b, fl, bdelta=None):
             per = min(len(srcs_b), (2**31 - 2) // g.n)
-            bsched = og.Schedule(delta=d, update=og.OG_EAGER_WITH_FUSION, flags=fl,
+            bsched = og.Schedule(delta=bdelta or d, update=og.OG_EAGER_WITH_FUSION, flags=fl,
                                  queue_capacity=max(1 << 22, per * (1 << 21)))
             og.sssp_batch(dg, srcs_b[:per], bsched, ws=bws, pred=False)  # warm-up
             torch.cuda.synchronize()
@@ -711,7 +711,7 @@ def main() -> int:
                 "queries": len(srcs_b), "queries_per_launch": per, "ms_total": round(bms, 3),
                 "ms_per_query": round(bms / len(srcs_b), 3),
                 "gteps": round(bst["reached_edges"] / (bms * 1e-3) / 1e9, 4), "engine_ms": round(bst["engine_ms"], 3),
-                "rounds": bst["rounds"],
+                "rounds": bst["rounds"], "delta": bsched.delta,
                 "alg_roofline_frac": round(balg / (bst["engine_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
             print(f"[bench] {name}: {bms:.1f} ms ({bms / len(srcs_b):.2f} ms/query)", file=sys.stderr, flush=True)
             return variants[name]
@@ -723,9 +723,17 @@ def main() -> int:
         for nb in BATCH_SIZES:
             if nb != nq:
                 batch_leg(f"batched_flat_{nb}", bsrcs_all[:nb], FLAT)
+        # the same batch at the headline launch's Delta (smaller buckets pay
+        # in batched launches, whose teams run rounds of their own), against
+        # the serial legs at their own best Delta
+        if args.delta != d:
+            b = batch_leg(f"batched_degree_bins_d{args.delta}", bsrcs, TB, args.delta)
+            b["vs_serial"] = round(variants["serial_degree_bins"]["ms_per_query"] / b["ms_per_query"], 2)
         variants["batched_sources"] = (f"batched and serial legs: the same {nq} sources (seed 1; the first "
-                                       f"{len(srcs)} are the headline's), same load balancing on both sides; "
-                                       f"batched_flat_<k>: the first k of the same stream")
+                                       f"{len(srcs)} are the headline's), same load balancing and Delta on both "
+                                       f"sides; batched_flat_<k>: the first k of the same stream; "
+                                       f"batched_degree_bins_d<D>: the batch at the headline's Delta D against "
+                                       f"the serial legs at theirs")
         variants["batched_vs_serial"] = max(variants["batched_flat"]["vs_serial"],
                                             variants["batched_degree_bins"]["vs_serial"])
         del bws
